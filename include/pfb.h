@@ -1,0 +1,197 @@
+/*
+ * pfb.h -- C ABI of the MI355X (gfx950) polyphase filter bank library.
+ *
+ * The library computes the two-step polyphase filter bank of Sec. 2:
+ *
+ *   raw spectra --FIR--> filtered spectra --DFT--> frequency spectra
+ *
+ * Data model (Sec. 2 and Sec. 3.1). A stream of complex samples is split into
+ * spectra of C channels, contiguous in channels. Complex values are stored as
+ * interleaved (re, im) pairs of the element type. For one plan:
+ *
+ *   x     [batch][spectra + taps - 1][channels]  complex, element type `dtype`
+ *   taps  [taps][channels]                       float32, h[t*C + c]
+ *   y     [batch][spectra][channels]             complex float32 (filtered)
+ *   Y     [batch][spectra][channels]             complex float32 (frequency)
+ *
+ * FIR (Sec. 3.2, Algorithm 1), in "valid" mode (S filtered spectra from
+ * S+T-1 raw spectra, no zero padding, no state between calls):
+ *   y[b][s][c] = sum_{t=0}^{T-1} h[t*C + c] * x[b][s+t][c]
+ * accumulated in float32 in ascending t. Coefficients are real, unique per
+ * (tap, channel) and float32 for every input type (Sec. 3.1).
+ * DFT (Sec. 2, Eq. (2)), per filtered spectrum, unnormalised, bins in natural
+ * order 0..C-1:
+ *   Y[b][s][m] = sum_{n=0}^{C-1} y[b][s][n] * exp(-2 pi i n m / C)
+ *
+ * Input element types (Sec. 3.1: 32-, 16- and 8-bit input): complex float32,
+ * complex int16, complex int8 (signed) and complex float16. Each sample is
+ * converted to float32 once, in registers; outputs are always complex
+ * float32 (Sec. 3.1).
+ *
+ * Memory. Every array argument is a DEVICE pointer owned by the caller, dense
+ * in the layout above and aligned to 16 bytes. The library never frees or
+ * keeps caller memory beyond a call. A plan owns its twiddle tables, tile
+ * tables, workspace and captured graphs; all of them are allocated when the
+ * plan is created, so the execute and backward calls allocate nothing.
+ *
+ * Streams. `stream` is a hipStream_t passed as void* (NULL = the default
+ * stream). All work of a call is enqueued on that stream in order; the calls
+ * return once the work is enqueued. A plan must not be used by two streams at
+ * the same time, and must be destroyed only after its work has completed.
+ *
+ * Errors. Every entry point returns a pfb_status. Arguments are validated on
+ * the host before anything is enqueued; a failed validation returns
+ * PFB_E_INVALID or PFB_E_UNSUPPORTED and enqueues nothing. Launch failures
+ * return PFB_E_HIP. Faults that happen on the device surface at the caller's
+ * next synchronisation. The library never aborts the process and no C++
+ * exception crosses this interface. pfb_last_error() returns a description of
+ * the last failure on the calling thread.
+ */
+#ifndef PFB_H
+#define PFB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PFB_OK = 0,
+    PFB_E_INVALID = 1,     /* bad argument: null pointer, size, alignment   */
+    PFB_E_UNSUPPORTED = 2, /* valid request outside what the library does   */
+    PFB_E_NOMEM = 3,       /* device or host allocation failed              */
+    PFB_E_HIP = 4,         /* a HIP runtime call or kernel launch failed    */
+    PFB_E_STATE = 5        /* plan of the wrong kind for this call          */
+} pfb_status;
+
+typedef enum {
+    PFB_C64 = 0,  /* complex float32: 8 bytes per sample                */
+    PFB_CI16 = 1, /* complex int16:   4 bytes per sample                */
+    PFB_CI8 = 2,  /* complex int8:    2 bytes per sample                */
+    PFB_CF16 = 3  /* complex float16: 4 bytes per sample                */
+} pfb_dtype;
+
+/* Plan flags. */
+enum {
+    PFB_FIR_ONLY = 1u,      /* stop after the FIR: y is the output, Y unused  */
+    PFB_NO_FUSE = 4u,       /* run FIR and FFT as separate passes             */
+    PFB_PLAIN = 8u          /* the untuned single-stream comparator: one FIR
+                               launch over the whole stream into a workspace,
+                               then one FFT launch; no fusion, no chunking   */
+};
+
+/* Limits. */
+#define PFB_MAX_TAPS 64
+#define PFB_MIN_FFT_CHANNELS 32
+#define PFB_MAX_FFT_CHANNELS 8192
+
+/* One filter-bank problem. `spectra` counts filtered (output) spectra; the
+ * input has spectra + taps - 1 raw spectra per stream. */
+typedef struct {
+    int32_t channels;  /* C >= 1; a power of two in [32, 8192] unless FIR_ONLY */
+    int32_t taps;      /* T in [1, PFB_MAX_TAPS]                               */
+    int64_t spectra;   /* S >= 1                                               */
+    int32_t batch;     /* B >= 1 independent streams                           */
+    int32_t dtype;     /* a pfb_dtype                                          */
+    uint32_t flags;    /* PFB_* flags                                          */
+} pfb_desc;
+
+typedef struct pfb_plan pfb_plan;
+
+/* Description of what a plan will run, for reports and tests. */
+typedef struct {
+    int32_t path;          /* 0 fused FIR+FFT, 1 split FIR then FFT, 2 FIR only */
+    int32_t fir_rows;      /* filtered spectra per FIR tile (S_B)              */
+    int32_t fir_cpt;       /* channels per thread in the FIR kernel            */
+    int32_t padded_taps;   /* taps rounded up to the kernel's template size    */
+    int64_t workspace_bytes;
+    int64_t chunk_rows;    /* spectra per FIR/FFT chunk on the split path      */
+} pfb_plan_info;
+
+/*
+ * Create a plan for one problem (all streams share C, T, S and the taps).
+ * Validates the descriptor, builds the FP64-derived twiddle table and
+ * allocates the workspace on the current HIP device.
+ * out: receives the plan (set to NULL on failure).
+ */
+pfb_status pfb_plan_create(const pfb_desc *desc, pfb_plan **out);
+
+/*
+ * Forward filter bank (Sec. 2 scheme).
+ *   x     device, [B][S+T-1][C] samples of the plan's dtype
+ *   taps  device, [T][C] float32
+ *   y     device, [B][S][C] complex float32, or NULL. When non-NULL the
+ *         filtered spectra are written there too (this forces the split
+ *         path). With PFB_FIR_ONLY, y is required and Y is ignored.
+ *   Y     device, [B][S][C] complex float32 (required unless FIR_ONLY)
+ * Outputs are overwritten. Inputs are not modified.
+ */
+pfb_status pfb_execute(pfb_plan *plan, const void *x, const float *taps, void *y, void *Y,
+                       void *stream);
+
+/*
+ * Adjoint (backward) of the forward filter bank for a real loss, given
+ * gY = dL/dRe(Y) + i dL/dIm(Y) (the frequency-spectra gradient):
+ *   gy[b][s][c] = sum_m gY[b][s][m] exp(+2 pi i m c / C)   (adjoint of Eq. (2))
+ *   gx[b][p][c] = sum_{t: 0 <= p-t < S} h[t*C+c] gy[b][p-t][c]  (adjoint of Alg. 1)
+ *   gh[t*C+c]   = sum_b sum_s Re(conj(gy[b][s][c]) x[b][s+t][c])
+ *   x     device, [B][S+T-1][C] complex float32 (the plan's dtype must be C64)
+ *   taps  device, [T][C] float32
+ *   gY    device, [B][S][C] complex float32
+ *   gx    device, [B][S+T-1][C] complex float32, or NULL to skip
+ *   gh    device, [T][C] float32, or NULL to skip; summed over the batch and
+ *         OVERWRITTEN (never accumulated into). Its reduction runs in a fixed
+ *         order, so repeated calls give identical bits.
+ * Requires a plan without FIR_ONLY.
+ */
+pfb_status pfb_backward(pfb_plan *plan, const void *x, const float *taps, const void *gY,
+                        void *gx, float *gh, void *stream);
+
+/*
+ * Many independent beams with their own C, T, S (one stream each, complex
+ * float32, C a power of two in [32, 8192]) in one persistent launch per
+ * call, recorded once into a HIP graph on first execution.
+ *   nbeams  >= 1; beams: host array of nbeams descriptors (batch must be 1,
+ *           dtype C64; flags ignored)
+ */
+pfb_status pfb_plan_create_batched(int32_t nbeams, const pfb_desc *beams, pfb_plan **out);
+
+/*
+ * Execute a batched plan.
+ *   x, taps, Y: HOST arrays of nbeams DEVICE pointers, beam i laid out as a
+ *   single stream of its own descriptor. The pointer values are baked into
+ *   the plan's graph on the first call; later calls with different pointers
+ *   rebuild the device-side pointer table (no allocation).
+ */
+pfb_status pfb_execute_batched(pfb_plan *plan, const void *const *x, const float *const *taps,
+                               void *const *Y, void *stream);
+
+/*
+ * Time the candidate tile configurations for one descriptor on the current
+ * device (temporary buffers are allocated and freed inside this call) and
+ * store the fastest in the tuning cache file `cache_path` (a small text file,
+ * created or updated). Plans created afterwards read the cache named by the
+ * PFB_TUNE_CACHE environment variable; a missing or unreadable cache means
+ * built-in defaults.
+ */
+pfb_status pfb_tune(const pfb_desc *desc, const char *cache_path);
+
+/* Report what a plan will run. */
+pfb_status pfb_plan_get_info(const pfb_plan *plan, pfb_plan_info *info);
+
+/* Release a plan and everything it owns. NULL is accepted. */
+pfb_status pfb_plan_destroy(pfb_plan *plan);
+
+/* Static description of a status code. */
+const char *pfb_status_str(pfb_status status);
+
+/* Description of the last failure on the calling thread ("" if none). */
+const char *pfb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PFB_H */

@@ -1,0 +1,554 @@
+// C ABI of the polyphase filter bank library (declared in include/pfb.h).
+//
+// Host side only: descriptor validation, plan construction (FP64-derived
+// twiddle tables, tile shapes, workspaces), and the launch sequence of each
+// call. Every step of the computation runs in the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pfb.h"
+#include "fft_schedule.h"
+#include "launch.h"
+#include "tune.h"
+
+using namespace pfb;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+pfb_status fail(pfb_status st, const std::string &msg)
+{
+    g_last_error = msg;
+    return st;
+}
+
+pfb_status hip_fail(hipError_t e, const char *what)
+{
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return PFB_E_HIP;
+}
+
+int bytes_per_sample(int dt)
+{
+    switch (dt) {
+    case PFB_C64: return 8;
+    case PFB_CI16: return 4;
+    case PFB_CI8: return 2;
+    case PFB_CF16: return 4;
+    default: return 0;
+    }
+}
+
+int ilog2_exact(int64_t v)
+{
+    if (v <= 0 || (v & (v - 1)))
+        return -1;
+    int l = 0;
+    while ((int64_t(1) << l) < v)
+        ++l;
+    return l;
+}
+
+int padded_taps(int T)
+{
+    int tp = 4;
+    while (tp < T)
+        tp *= 2;
+    return tp;
+}
+
+bool mul_ok(int64_t a, int64_t b, int64_t *out)
+{
+    if (a < 0 || b < 0)
+        return false;
+    if (a != 0 && b > INT64_MAX / a)
+        return false;
+    *out = a * b;
+    return true;
+}
+
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+} // namespace
+
+enum PlanKind { KIND_SINGLE = 1, KIND_BATCHED = 2 };
+enum Path { PATH_FUSED = 0, PATH_SPLIT = 1, PATH_FIR_ONLY = 2 };
+
+struct pfb_plan {
+    int kind = KIND_SINGLE;
+    pfb_desc d{};
+    int device = 0;
+    int log2c = -1;
+    int tp = 4;
+    Path path = PATH_SPLIT;
+    // FIR tiling (split path and backward)
+    int fir_sb = 256;
+    int fir_cpt = 1;
+    // fused tiling
+    int fused_sb = 0;
+    // split path chunking
+    int64_t chunk_rows = 0;
+    float2 *twiddle = nullptr;   // FFT twiddle table for C
+    float2 *ws_y = nullptr;      // filtered spectra workspace (split path)
+    int64_t ws_y_bytes = 0;
+    float2 *ws_gy = nullptr;     // backward: inverse-transformed gradient
+    int64_t ws_gy_bytes = 0;
+    float *ws_gh = nullptr;      // backward: tap-gradient partials
+    int64_t ws_gh_bytes = 0;
+    int gh_sb = 256;
+    // batched
+    struct Batched *batched = nullptr;
+};
+
+// ----------------------------------------------------------------------------
+// Twiddles
+// ----------------------------------------------------------------------------
+
+static pfb_status make_twiddles(int log2c, float2 **out)
+{
+    const FftSchedule sch(log2c);
+    const int n = sch.table_size() > 0 ? sch.table_size() : 1;
+    std::vector<float2> host((size_t)n, make_float2(1.0f, 0.0f));
+    for (int p = 1; p < sch.npass; ++p) {
+        const int R = sch.radix(p), L = sch.stride(p), RL = R * L;
+        for (int k = 0; k < L; ++k)
+            for (int i = 0; i < R; ++i) {
+                const int64_t e = ((int64_t)i * k) % RL; // exact integer reduction
+                const double a = -2.0 * M_PI * (double)e / (double)RL;
+                host[(size_t)sch.pass_offset(p) + (size_t)k * R + i] = make_float2((float)std::cos(a), (float)std::sin(a));
+            }
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, sizeof(float2) * (size_t)n);
+    if (e != hipSuccess)
+        return fail(PFB_E_NOMEM, std::string("hipMalloc(twiddles): ") + hipGetErrorString(e));
+    e = hipMemcpy(p, host.data(), sizeof(float2) * (size_t)n, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(p);
+        return hip_fail(e, "hipMemcpy(twiddles)");
+    }
+    *out = reinterpret_cast<float2 *>(p);
+    return PFB_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Validation
+// ----------------------------------------------------------------------------
+
+static pfb_status validate_desc(const pfb_desc *d, bool batched_beam)
+{
+    if (!d)
+        return fail(PFB_E_INVALID, "descriptor is NULL");
+    if (d->channels < 1)
+        return fail(PFB_E_INVALID, "channels must be >= 1");
+    if (d->taps < 1)
+        return fail(PFB_E_INVALID, "taps must be >= 1");
+    if (d->taps > PFB_MAX_TAPS)
+        return fail(PFB_E_UNSUPPORTED, "taps above PFB_MAX_TAPS");
+    if (d->spectra < 1)
+        return fail(PFB_E_INVALID, "spectra must be >= 1");
+    if (d->batch < 1)
+        return fail(PFB_E_INVALID, "batch must be >= 1");
+    if (bytes_per_sample(d->dtype) == 0)
+        return fail(PFB_E_INVALID, "unknown dtype");
+    const uint32_t known = PFB_FIR_ONLY | PFB_NO_FUSE | PFB_PLAIN;
+    if (!batched_beam && (d->flags & ~known))
+        return fail(PFB_E_INVALID, "unknown flag bits");
+    const bool fir_only = !batched_beam && (d->flags & PFB_FIR_ONLY);
+    if (!fir_only) {
+        const int l2 = ilog2_exact(d->channels);
+        if (l2 < 0 || d->channels < PFB_MIN_FFT_CHANNELS || d->channels > PFB_MAX_FFT_CHANNELS)
+            return fail(PFB_E_UNSUPPORTED, "the FFT needs channels a power of two in [32, 8192]");
+    }
+    // every element count must fit comfortably in int64
+    int64_t rows = d->spectra + d->taps - 1, t = 0, u = 0;
+    if (!mul_ok(rows, d->channels, &t) || !mul_ok(t, d->batch, &u) || !mul_ok(u, 16, &t))
+        return fail(PFB_E_INVALID, "problem size overflows 64-bit byte counts");
+    return PFB_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Plans
+// ----------------------------------------------------------------------------
+
+static void free_plan_memory(pfb_plan *p)
+{
+    if (p->twiddle)
+        (void)hipFree(p->twiddle);
+    if (p->ws_y)
+        (void)hipFree(p->ws_y);
+    if (p->ws_gy)
+        (void)hipFree(p->ws_gy);
+    if (p->ws_gh)
+        (void)hipFree(p->ws_gh);
+    p->twiddle = nullptr;
+    p->ws_y = p->ws_gy = nullptr;
+    p->ws_gh = nullptr;
+}
+
+static pfb_status dev_alloc(void **p, int64_t bytes, const char *what)
+{
+    *p = nullptr;
+    if (bytes <= 0)
+        return PFB_OK;
+    hipError_t e = hipMalloc(p, (size_t)bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(PFB_E_NOMEM, std::string("hipMalloc(") + what + "): " + hipGetErrorString(e));
+    }
+    return PFB_OK;
+}
+
+static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Rows per fused tile: about one tile per CU in a single wave of tiles for
+// the whole job, a multiple of the chunk height, at least one chunk.
+static int choose_fused_sb(const pfb_desc &d, int rb)
+{
+    const int64_t total = (int64_t)d.batch * d.spectra;
+    int64_t sb = ceil_div(total, 256);
+    sb = ceil_div(sb, rb) * rb;
+    if (sb > d.spectra)
+        sb = ceil_div(d.spectra, rb) * rb;
+    if (sb < rb)
+        sb = rb;
+    if (sb > 8192)
+        sb = 8192;
+    return (int)sb;
+}
+
+static pfb_status plan_single(const pfb_desc *d, pfb_plan *p)
+{
+    p->kind = KIND_SINGLE;
+    p->d = *d;
+    (void)hipGetDevice(&p->device);
+    p->tp = padded_taps(d->taps);
+    const bool fir_only = d->flags & PFB_FIR_ONLY;
+    p->log2c = fir_only ? -1 : ilog2_exact(d->channels);
+
+    TuneEntry te;
+    const bool tuned = tune_lookup(*d, &te);
+    p->fir_cpt = (d->channels % 2 == 0) ? 2 : 1;
+    p->fir_sb = 256;
+    if (tuned) {
+        if (te.fir_cpt == 1 || (te.fir_cpt == 2 && d->channels % 2 == 0))
+            p->fir_cpt = te.fir_cpt;
+        if (te.fir_sb >= 16 && te.fir_sb <= 8192)
+            p->fir_sb = te.fir_sb;
+    }
+    if (d->flags & PFB_PLAIN) {
+        p->fir_cpt = 1;
+        p->fir_sb = 256;
+    }
+
+    if (fir_only) {
+        p->path = PATH_FIR_ONLY;
+    } else if (!(d->flags & (PFB_NO_FUSE | PFB_PLAIN)) && fused_supported(d->dtype, p->tp, p->log2c) &&
+               !(tuned && te.path == PATH_SPLIT)) {
+        p->path = PATH_FUSED;
+        const int rb = fused_rows_per_chunk(p->tp, p->log2c);
+        p->fused_sb = choose_fused_sb(*d, rb);
+        if (tuned && te.fused_sb >= rb && te.fused_sb % rb == 0)
+            p->fused_sb = te.fused_sb;
+    } else {
+        p->path = PATH_SPLIT;
+    }
+
+    pfb_status st;
+    if (!fir_only) {
+        st = make_twiddles(p->log2c, &p->twiddle);
+        if (st != PFB_OK)
+            return st;
+        // Split path workspace: the whole filtered-spectra array for the
+        // plain comparator; otherwise chunks of about 64 MiB, small enough to
+        // stay in the last-level cache between the FIR and FFT passes.
+        const int64_t row_bytes = (int64_t)d->channels * 8;
+        if (d->flags & PFB_PLAIN) {
+            p->chunk_rows = d->spectra;
+        } else {
+            int64_t target = (int64_t)64 << 20;
+            if (tuned && te.chunk_mib > 0)
+                target = (int64_t)te.chunk_mib << 20;
+            p->chunk_rows = target / (row_bytes * d->batch);
+            if (p->chunk_rows < 1)
+                p->chunk_rows = 1;
+            if (p->chunk_rows > d->spectra)
+                p->chunk_rows = d->spectra;
+        }
+        p->ws_y_bytes = p->chunk_rows * row_bytes * d->batch;
+        st = dev_alloc(reinterpret_cast<void **>(&p->ws_y), p->ws_y_bytes, "split workspace");
+        if (st != PFB_OK)
+            return st;
+        if (d->dtype == PFB_C64) {
+            p->ws_gy_bytes = (int64_t)d->batch * d->spectra * row_bytes;
+            st = dev_alloc(reinterpret_cast<void **>(&p->ws_gy), p->ws_gy_bytes, "backward workspace");
+            if (st != PFB_OK)
+                return st;
+            p->gh_sb = 256;
+            const int64_t n_tiles = ceil_div(d->spectra, p->gh_sb);
+            p->ws_gh_bytes = (int64_t)d->batch * n_tiles * d->taps * d->channels * 4;
+            st = dev_alloc(reinterpret_cast<void **>(&p->ws_gh), p->ws_gh_bytes, "tap-gradient partials");
+            if (st != PFB_OK)
+                return st;
+        }
+    }
+    return PFB_OK;
+}
+
+extern "C" pfb_status pfb_plan_create(const pfb_desc *desc, pfb_plan **out)
+{
+    if (!out)
+        return fail(PFB_E_INVALID, "out is NULL");
+    *out = nullptr;
+    pfb_status st = validate_desc(desc, false);
+    if (st != PFB_OK)
+        return st;
+    pfb_plan *p = new (std::nothrow) pfb_plan();
+    if (!p)
+        return fail(PFB_E_NOMEM, "host allocation of the plan failed");
+    st = plan_single(desc, p);
+    if (st != PFB_OK) {
+        free_plan_memory(p);
+        delete p;
+        return st;
+    }
+    *out = p;
+    return PFB_OK;
+}
+
+extern "C" pfb_status pfb_plan_get_info(const pfb_plan *p, pfb_plan_info *info)
+{
+    if (!p || !info)
+        return fail(PFB_E_INVALID, "NULL argument");
+    if (p->kind != KIND_SINGLE)
+        return fail(PFB_E_STATE, "not a single-problem plan");
+    info->path = (int32_t)p->path;
+    info->fir_rows = p->path == PATH_FUSED ? p->fused_sb : p->fir_sb;
+    info->fir_cpt = p->fir_cpt;
+    info->padded_taps = p->tp;
+    info->workspace_bytes = p->ws_y_bytes + p->ws_gy_bytes + p->ws_gh_bytes;
+    info->chunk_rows = p->chunk_rows;
+    return PFB_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Forward
+// ----------------------------------------------------------------------------
+
+// FIR over output rows [s_a, s_a + n) of every stream into y, where output
+// row s of stream b lands at y + b*y_bstride + (s - s_a)*C.
+static hipError_t run_fir(const pfb_plan *p, const void *x, const float *h, float2 *y, int64_t s_a, int64_t n,
+                          int64_t y_bstride, hipStream_t st)
+{
+    const pfb_desc &d = p->d;
+    FirArgs a{};
+    a.x = x;
+    a.h = h;
+    a.y = y;
+    a.C = d.channels;
+    a.T = d.taps;
+    a.B = d.batch;
+    a.SB = p->fir_sb;
+    a.n_tiles = (int)ceil_div(n, a.SB);
+    a.n_cchunks = (int)ceil_div(d.channels, 64 * p->fir_cpt);
+    a.in_rows = d.spectra + d.taps - 1;
+    a.in_bstride = a.in_rows * d.channels;
+    a.shift = p->tp - d.taps;
+    a.out_first = s_a;
+    a.out_count = n;
+    a.y_bstride = y_bstride;
+    return launch_fir(a, d.dtype, p->tp, p->fir_cpt, false, st);
+}
+
+static hipError_t run_fft(const pfb_plan *p, const float2 *in, float2 *out, int64_t nrows, int64_t rows_per_group,
+                          int64_t in_gstride, int64_t out_gstride, bool inv, hipStream_t st)
+{
+    FftArgs a{};
+    a.in = in;
+    a.out = out;
+    a.tw = p->twiddle;
+    a.nrows = nrows;
+    a.rows_per_group = rows_per_group;
+    a.in_gstride = in_gstride;
+    a.out_gstride = out_gstride;
+    return launch_fft(a, p->log2c, inv, st);
+}
+
+extern "C" pfb_status pfb_execute(pfb_plan *p, const void *x, const float *taps, void *y, void *Y, void *stream)
+{
+    if (!p)
+        return fail(PFB_E_INVALID, "plan is NULL");
+    if (p->kind != KIND_SINGLE)
+        return fail(PFB_E_STATE, "pfb_execute needs a single-problem plan");
+    if (!x || !taps)
+        return fail(PFB_E_INVALID, "x and taps must be non-NULL");
+    const pfb_desc &d = p->d;
+    const bool fir_only = p->path == PATH_FIR_ONLY;
+    if (fir_only && !y)
+        return fail(PFB_E_INVALID, "a FIR-only plan needs y");
+    if (!fir_only && !Y)
+        return fail(PFB_E_INVALID, "Y must be non-NULL");
+    if (!aligned16(x) || !aligned16(taps) || (y && !aligned16(y)) || (!fir_only && !aligned16(Y)))
+        return fail(PFB_E_INVALID, "device pointers must be 16-byte aligned");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int64_t C = d.channels, S = d.spectra;
+    hipError_t e;
+
+    if (fir_only) {
+        e = run_fir(p, x, taps, reinterpret_cast<float2 *>(y), 0, S, S * C, st);
+        return e == hipSuccess ? PFB_OK : hip_fail(e, "FIR launch");
+    }
+    float2 *Yo = reinterpret_cast<float2 *>(Y);
+    if (p->path == PATH_FUSED && !y) {
+        FusedArgs a{};
+        a.x = x;
+        a.h = taps;
+        a.Y = Yo;
+        a.tw = p->twiddle;
+        a.T = d.taps;
+        a.B = d.batch;
+        a.SB = p->fused_sb;
+        a.n_tiles = (int)ceil_div(S, a.SB);
+        a.S = S;
+        e = launch_fused(a, d.dtype, p->tp, p->log2c, st);
+        return e == hipSuccess ? PFB_OK : hip_fail(e, "fused FIR+FFT launch");
+    }
+    if (y) {
+        // the caller keeps the filtered spectra: whole FIR, then whole FFT
+        float2 *yo = reinterpret_cast<float2 *>(y);
+        e = run_fir(p, x, taps, yo, 0, S, S * C, st);
+        if (e == hipSuccess)
+            e = run_fft(p, yo, Yo, (int64_t)d.batch * S, S, S * C, S * C, false, st);
+        return e == hipSuccess ? PFB_OK : hip_fail(e, "split FIR/FFT launch");
+    }
+    // chunked split path through the plan's workspace
+    for (int64_t s_a = 0; s_a < S; s_a += p->chunk_rows) {
+        const int64_t n = (S - s_a) < p->chunk_rows ? (S - s_a) : p->chunk_rows;
+        e = run_fir(p, x, taps, p->ws_y, s_a, n, n * C, st);
+        if (e != hipSuccess)
+            return hip_fail(e, "FIR launch");
+        e = run_fft(p, p->ws_y, Yo + s_a * C, (int64_t)d.batch * n, n, n * C, S * C, false, st);
+        if (e != hipSuccess)
+            return hip_fail(e, "FFT launch");
+    }
+    return PFB_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Backward
+// ----------------------------------------------------------------------------
+
+extern "C" pfb_status pfb_backward(pfb_plan *p, const void *x, const float *taps, const void *gY, void *gx,
+                                   float *gh, void *stream)
+{
+    if (!p)
+        return fail(PFB_E_INVALID, "plan is NULL");
+    if (p->kind != KIND_SINGLE)
+        return fail(PFB_E_STATE, "pfb_backward needs a single-problem plan");
+    if (p->path == PATH_FIR_ONLY)
+        return fail(PFB_E_STATE, "pfb_backward needs a plan with the FFT step");
+    const pfb_desc &d = p->d;
+    if (d.dtype != PFB_C64)
+        return fail(PFB_E_UNSUPPORTED, "pfb_backward needs complex float32 input");
+    if (!gY || !taps || (gh && !x))
+        return fail(PFB_E_INVALID, "gY and taps (and x for gh) must be non-NULL");
+    if (!aligned16(gY) || !aligned16(taps) || (x && !aligned16(x)) || (gx && !aligned16(gx)) ||
+        (gh && !aligned16(gh)))
+        return fail(PFB_E_INVALID, "device pointers must be 16-byte aligned");
+    if (!gx && !gh)
+        return PFB_OK;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int64_t C = d.channels, S = d.spectra, T = d.taps;
+    hipError_t e;
+    // 1. gy = unnormalised inverse DFT of gY (adjoint of Eq. (2))
+    e = run_fft(p, reinterpret_cast<const float2 *>(gY), p->ws_gy, (int64_t)d.batch * S, S, S * C, S * C, true, st);
+    if (e != hipSuccess)
+        return hip_fail(e, "inverse FFT launch");
+    // 2. gx = adjoint FIR: reversed taps over gy, zero outside [0, S)
+    if (gx) {
+        FirArgs a{};
+        a.x = p->ws_gy;
+        a.h = taps;
+        a.y = reinterpret_cast<float2 *>(gx);
+        a.C = d.channels;
+        a.T = d.taps;
+        a.B = d.batch;
+        a.SB = p->fir_sb;
+        const int64_t rows = S + T - 1;
+        a.n_tiles = (int)ceil_div(rows, a.SB);
+        a.n_cchunks = (int)ceil_div(C, 64 * p->fir_cpt);
+        a.in_rows = S;
+        a.in_bstride = S * C;
+        a.shift = (p->tp - T) + T - 1;
+        a.out_first = 0;
+        a.out_count = rows;
+        a.y_bstride = rows * C;
+        e = launch_fir(a, PFB_C64, p->tp, p->fir_cpt, true, st);
+        if (e != hipSuccess)
+            return hip_fail(e, "adjoint FIR launch");
+    }
+    // 3. gh = sum over streams and spectra of Re(conj(gy) x), two fixed-order stages
+    if (gh) {
+        GhArgs a{};
+        a.x = reinterpret_cast<const float2 *>(x);
+        a.gy = p->ws_gy;
+        a.part = p->ws_gh;
+        a.C = d.channels;
+        a.T = d.taps;
+        a.B = d.batch;
+        a.SB = p->gh_sb;
+        a.n_tiles = (int)ceil_div(S, a.SB);
+        a.n_cchunks = (int)ceil_div(C, 64);
+        a.S = S;
+        e = launch_gh(a, p->tp, gh, st);
+        if (e != hipSuccess)
+            return hip_fail(e, "tap-gradient launch");
+    }
+    return PFB_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Misc
+// ----------------------------------------------------------------------------
+
+extern "C" pfb_status pfb_plan_destroy(pfb_plan *p)
+{
+    if (!p)
+        return PFB_OK;
+    if (p->batched)
+        batched_free(p->batched);
+    free_plan_memory(p);
+    delete p;
+    return PFB_OK;
+}
+
+extern "C" const char *pfb_status_str(pfb_status s)
+{
+    switch (s) {
+    case PFB_OK: return "PFB_OK";
+    case PFB_E_INVALID: return "PFB_E_INVALID: invalid argument";
+    case PFB_E_UNSUPPORTED: return "PFB_E_UNSUPPORTED: unsupported request";
+    case PFB_E_NOMEM: return "PFB_E_NOMEM: allocation failed";
+    case PFB_E_HIP: return "PFB_E_HIP: HIP runtime error";
+    case PFB_E_STATE: return "PFB_E_STATE: wrong plan kind for this call";
+    default: return "unknown pfb_status";
+    }
+}
+
+extern "C" const char *pfb_last_error(void) { return g_last_error.c_str(); }
+
+// Internal hooks for the batched and tuning modules.
+pfb_status pfb_internal_fail(pfb_status st, const char *msg) { return fail(st, msg); }
+pfb_status pfb_internal_validate(const pfb_desc *d, bool batched_beam) { return validate_desc(d, batched_beam); }
+pfb_plan *pfb_internal_new_plan() { return new (std::nothrow) pfb_plan(); }
+void pfb_internal_set_batched(pfb_plan *p, Batched *b) { p->kind = KIND_BATCHED; p->batched = b; }
+Batched *pfb_internal_get_batched(pfb_plan *p) { return p->kind == KIND_BATCHED ? p->batched : nullptr; }

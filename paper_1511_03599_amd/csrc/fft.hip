@@ -1,0 +1,70 @@
+// Stand-alone batched C-point FFT (the DFT step of Sec. 2, Eq. (2)) for the
+// split path: reads complex float32 rows, writes their transforms. One group
+// of G lanes per row (several rows per block when G < 256); the Stockham
+// passes exchange data through the group's padded LDS row.
+#include "fft_device.h"
+#include "launch.h"
+
+namespace pfb {
+
+template <int LOG2C> struct FftKernelShape {
+    using FL = FftLanes<LOG2C>;
+    static constexpr int G = FL::G;
+    static constexpr int NT = G > 256 ? G : 256; // threads per block
+    static constexpr int F = NT / G;             // rows per block
+};
+
+template <int LOG2C, bool INV>
+__global__ __launch_bounds__(FftKernelShape<LOG2C>::NT) void fft_kernel(FftArgs a)
+{
+    using K = FftKernelShape<LOG2C>;
+    constexpr int G = K::G;
+    constexpr int C = 1 << LOG2C;
+    using S = FftShape<LOG2C, G>;
+    __shared__ float2 lds[K::F * S::PADDED];
+
+    const int gid = (int)threadIdx.x / G;
+    const int lane = (int)threadIdx.x % G;
+    const int64_t row = (int64_t)blockIdx.x * K::F + gid;
+    // With G > 64 there is one row per block, so this exit is block-uniform;
+    // with G <= 64 the passes use no block-wide barrier.
+    if (row >= a.nrows)
+        return;
+    const int64_t g = row / a.rows_per_group, r = row % a.rows_per_group;
+    const float2 *in = a.in + g * a.in_gstride + r * C;
+    float2 *out = a.out + g * a.out_gstride + r * C;
+    fft_run<LOG2C, G, INV, false>(
+        lane, lds + gid * S::PADDED, a.tw, [&](int idx) { return in[idx]; },
+        [&](int idx, float2 v) { out[idx] = v; });
+}
+
+template <int LOG2C> static hipError_t launch_fft_t(const FftArgs &a, bool inv, hipStream_t st)
+{
+    using K = FftKernelShape<LOG2C>;
+    const int64_t blocks = (a.nrows + K::F - 1) / K::F;
+    if (blocks <= 0)
+        return hipSuccess;
+    if (inv)
+        hipLaunchKernelGGL((fft_kernel<LOG2C, true>), dim3((unsigned)blocks), dim3(K::NT), 0, st, a);
+    else
+        hipLaunchKernelGGL((fft_kernel<LOG2C, false>), dim3((unsigned)blocks), dim3(K::NT), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fft(const FftArgs &a, int log2c, bool inv, hipStream_t st)
+{
+    switch (log2c) {
+    case 5: return launch_fft_t<5>(a, inv, st);
+    case 6: return launch_fft_t<6>(a, inv, st);
+    case 7: return launch_fft_t<7>(a, inv, st);
+    case 8: return launch_fft_t<8>(a, inv, st);
+    case 9: return launch_fft_t<9>(a, inv, st);
+    case 10: return launch_fft_t<10>(a, inv, st);
+    case 11: return launch_fft_t<11>(a, inv, st);
+    case 12: return launch_fft_t<12>(a, inv, st);
+    case 13: return launch_fft_t<13>(a, inv, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+} // namespace pfb

@@ -1,0 +1,245 @@
+// Stockham autosort FFT for one C-point transform held by a group of G lanes
+// (C a power of two, E = C/G elements per lane, E in {4, 8, 16}).
+//
+// The transform is the DFT of Sec. 2, Eq. (2): unnormalised, bins in natural
+// order, exp(-2 pi i n m / C). The inverse (exp(+...), unnormalised) is the
+// same network applied to conjugated input with conjugated output.
+//
+// Each pass of radix R with stride L (the product of the radices of earlier
+// passes) lets every butterfly j (0 <= j < C/R) read elements j + i*C/R,
+// multiply element i by W_{R L}^{i k} (k = j mod L), run an R-point DFT in
+// registers and write element i to (j - k) R + k + i L. After the last pass
+// the output is in natural order. The first pass reads its inputs straight
+// from the source (global memory or an LDS row) and the last pass writes its
+// outputs straight to the destination with consecutive lanes on consecutive
+// elements, so both are coalesced. Between passes the data goes through this
+// group's LDS row, padded by one element in sixteen against bank conflicts.
+//
+// Twiddles come from a per-transform-size table computed in FP64 on the host
+// and rounded once to float32: for every pass P > 0 (radix R, stride L) it
+// holds W_{RL}^{ik} = exp(-2 pi i (ik mod RL) / (RL)) at
+// [pass_offset(P) + k*R + i], so the R twiddles of one butterfly are
+// contiguous and load as R/2 aligned 16-byte vectors.
+#pragma once
+
+#include <utility>
+
+#include "device_common.h"
+#include "fft_schedule.h"
+
+namespace pfb {
+
+template <int N, class F, int... Is>
+__device__ __forceinline__ void sfor_impl(F &&f, std::integer_sequence<int, Is...>)
+{
+    (f(std::integral_constant<int, Is>{}), ...);
+}
+// Compile-time loop: calls f(std::integral_constant<int, i>) for i = 0..N-1.
+template <int N, class F> __device__ __forceinline__ void sfor(F &&f)
+{
+    sfor_impl<N>(f, std::make_integer_sequence<int, N>{});
+}
+
+// cos(2 pi e / 16) and sin(2 pi e / 16).
+constexpr float cos16(int e)
+{
+    constexpr float c[16] = {1.0f, 0.92387953251128674f, 0.70710678118654757f, 0.38268343236508978f,
+                             0.0f, -0.38268343236508978f, -0.70710678118654757f, -0.92387953251128674f,
+                             -1.0f, -0.92387953251128674f, -0.70710678118654757f, -0.38268343236508978f,
+                             0.0f, 0.38268343236508978f, 0.70710678118654757f, 0.92387953251128674f};
+    return c[e & 15];
+}
+constexpr float sin16(int e) { return cos16(e - 4); }
+
+// v * W_N^E with W_N = exp(-2 pi i / N), N dividing 16.
+template <int N, int E> __device__ __forceinline__ float2 twc(float2 v)
+{
+    constexpr int e = (E * (16 / N)) & 15;
+    if constexpr (e == 0) {
+        return v;
+    } else if constexpr (e == 4) {
+        return mul_mi(v);
+    } else if constexpr (e == 8) {
+        return make_float2(-v.x, -v.y);
+    } else if constexpr (e == 12) {
+        return mul_pi(v);
+    } else if constexpr (e == 2 || e == 6 || e == 10 || e == 14) {
+        // W = (c, -s) with |c| = |s| = sqrt(1/2)
+        constexpr float c = cos16(e), s = sin16(e);
+        return make_float2((v.x * c) + (v.y * s), (v.y * c) - (v.x * s));
+    } else {
+        constexpr float c = cos16(e), s = sin16(e);
+        return make_float2(__builtin_fmaf(v.x, c, v.y * s), __builtin_fmaf(v.y, c, -(v.x * s)));
+    }
+}
+
+template <int R> struct Dft;
+template <> struct Dft<1> {
+    static __device__ __forceinline__ void run(float2 *) {}
+};
+template <> struct Dft<2> {
+    static __device__ __forceinline__ void run(float2 *v)
+    {
+        float2 a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    }
+};
+template <> struct Dft<4> {
+    static __device__ __forceinline__ void run(float2 *v)
+    {
+        float2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+        float2 t2 = cadd(v[1], v[3]), t3 = mul_mi(csub(v[1], v[3]));
+        v[0] = cadd(t0, t2);
+        v[2] = csub(t0, t2);
+        v[1] = cadd(t1, t3);
+        v[3] = csub(t1, t3);
+    }
+};
+
+// R = N1 * N2 by one Cooley-Tukey step: n = N2 n1 + n2, k = k1 + N1 k2.
+template <int N1, int N2> __device__ __forceinline__ void dft_ct(float2 *v)
+{
+    constexpr int N = N1 * N2;
+    float2 a[N2][N1];
+    sfor<N2>([&](auto n2) {
+        sfor<N1>([&](auto n1) { a[n2][n1] = v[N2 * n1 + n2]; });
+        Dft<N1>::run(a[n2]);
+        sfor<N1>([&](auto k1) {
+            a[n2][k1] = twc<N, decltype(n2)::value * decltype(k1)::value>(a[n2][k1]);
+        });
+    });
+    sfor<N1>([&](auto k1) {
+        float2 b[N2];
+        sfor<N2>([&](auto n2) { b[n2] = a[n2][k1]; });
+        Dft<N2>::run(b);
+        sfor<N2>([&](auto k2) { v[k1 + N1 * k2] = b[k2]; });
+    });
+}
+template <> struct Dft<8> {
+    static __device__ __forceinline__ void run(float2 *v) { dft_ct<4, 2>(v); }
+};
+template <> struct Dft<16> {
+    static __device__ __forceinline__ void run(float2 *v) { dft_ct<4, 4>(v); }
+};
+
+// Synchronise the lanes of one FFT group between LDS passes.
+template <int G> __device__ __forceinline__ void group_sync()
+{
+    if constexpr (G > 64) {
+        __syncthreads();
+    } else {
+        // One wave: LDS operations of a wave complete in order; only the
+        // compiler has to be kept from moving accesses across this point.
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+template <int LOG2C, int G> struct FftShape {
+    static constexpr int C = 1 << LOG2C;
+    static constexpr int E = C / G;
+    static constexpr FftSchedule SCHED{LOG2C};
+    static constexpr int NPASS = SCHED.npass;
+    static constexpr int PADDED = C + C / 16; // LDS float2 per transform
+    static_assert(E == SCHED.e, "elements per lane");
+    static_assert(G * E == C, "shape");
+
+    static __device__ __forceinline__ int pad(int idx) { return idx + (idx >> 4); }
+    static constexpr int radix(int p) { return SCHED.radix(p); }
+    static constexpr int stride(int p) { return SCHED.stride(p); }
+    static constexpr int pass_offset(int p) { return SCHED.pass_offset(p); }
+};
+
+// Run one transform. `src(idx)` returns input element idx (first pass);
+// `dst(idx, v)` receives output element idx (last pass). When SRC_IN_LDS the
+// first pass reads this group's own LDS row (so in a multi-wave group the
+// lanes synchronise before overwriting it). INV selects exp(+...).
+template <int LOG2C, int G, bool INV, bool SRC_IN_LDS, class Src, class Dst>
+__device__ __forceinline__ void fft_run(int lane, float2 *lds, const float2 *__restrict__ tw, Src &&src,
+                                        Dst &&dst)
+{
+    using S = FftShape<LOG2C, G>;
+    constexpr int C = S::C;
+    constexpr int E = S::E;
+    float2 v[E];
+
+    sfor<S::NPASS>([&](auto pp) {
+        constexpr int P = decltype(pp)::value;
+        constexpr int R = S::radix(P);
+        constexpr int L = S::stride(P);
+        constexpr int NB = E / R;
+        constexpr int CR = C / R;
+
+        // gather
+        sfor<NB>([&](auto q) {
+            const int j = lane + G * decltype(q)::value;
+            sfor<R>([&](auto i) {
+                const int idx = j + decltype(i)::value * CR;
+                float2 t;
+                if constexpr (P == 0) {
+                    t = src(idx);
+                    if constexpr (INV)
+                        t = conj2(t);
+                } else {
+                    t = lds[S::pad(idx)];
+                }
+                v[decltype(q)::value * R + decltype(i)::value] = t;
+            });
+        });
+        if constexpr (G > 64 && P < S::NPASS - 1 && (P > 0 || SRC_IN_LDS))
+            group_sync<G>(); // every lane has read before any lane overwrites
+
+        // twiddle and butterfly
+        sfor<NB>([&](auto q) {
+            constexpr int Q = decltype(q)::value;
+            const int j = lane + G * Q;
+            if constexpr (L > 1) {
+                const int k = j & (L - 1);
+                const float4 *wp = reinterpret_cast<const float4 *>(tw + S::pass_offset(P) + k * R);
+                sfor<R / 2>([&](auto hh) {
+                    constexpr int H = decltype(hh)::value;
+                    const float4 w2 = wp[H];
+                    if constexpr (H > 0)
+                        v[Q * R + 2 * H] = cmul(v[Q * R + 2 * H], make_float2(w2.x, w2.y));
+                    v[Q * R + 2 * H + 1] = cmul(v[Q * R + 2 * H + 1], make_float2(w2.z, w2.w));
+                });
+            }
+            Dft<R>::run(&v[Q * R]);
+        });
+
+        // scatter
+        if constexpr (P == S::NPASS - 1) {
+            sfor<NB>([&](auto q) {
+                const int j = lane + G * decltype(q)::value;
+                sfor<R>([&](auto i) {
+                    float2 t = v[decltype(q)::value * R + decltype(i)::value];
+                    if constexpr (INV)
+                        t = conj2(t);
+                    dst(j + decltype(i)::value * CR, t);
+                });
+            });
+        } else {
+            sfor<NB>([&](auto q) {
+                const int j = lane + G * decltype(q)::value;
+                const int k = j & (L - 1);
+                const int o = (j - k) * R + k;
+                sfor<R>([&](auto i) {
+                    lds[S::pad(o + decltype(i)::value * L)] = v[decltype(q)::value * R + decltype(i)::value];
+                });
+            });
+            group_sync<G>();
+        }
+    });
+}
+
+// Lanes per transform: C <= 1024 lives in one wave (or part of one); larger C
+// spans C/16 lanes over several waves.
+template <int LOG2C> struct FftLanes {
+    static constexpr int C = 1 << LOG2C;
+    static constexpr int E = fft_elems_per_lane(LOG2C);
+    static constexpr int G = C / E;
+};
+
+} // namespace pfb

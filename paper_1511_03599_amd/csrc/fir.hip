@@ -1,0 +1,287 @@
+// Polyphase FIR kernels for gfx950.
+//
+// FIR of Sec. 3.2 (Algorithm 1): y[s][c] = sum_t h[t*C + c] x[s+t][c].
+//
+// Layout and reuse. Samples are contiguous in channels (Sec. 3.1), so one
+// wave owns 64*CPT consecutive channels of a tile of S_B filtered spectra
+// (the blocking of Sec. 3.2, Fig. 5, with C_B = 64*CPT) and every row load is
+// one coalesced 512*CPT-byte access. Each lane walks down its channels and
+// keeps the last TP raw samples of each channel in registers, so every raw
+// sample is loaded from HBM once per tile and used for all T taps (the reuse
+// principle of Sec. 3.2); only the (T-1)-row halo at the tile start is read
+// twice. The taps of the lane's channels also stay in registers. Rows are
+// prefetched D outputs ahead. Low-precision samples are converted to float32
+// once, at load.
+//
+// Taps are padded up to the template size TP >= T by leading zeros, so one
+// kernel serves every T <= TP: with off = TP - T, window slot j of output s
+// holds input row s + j - shift and carries tap j - off (zero for j < off).
+// Rows outside [0, in_rows) read as zero. The same kernel computes the
+// adjoint in the samples (REV: taps reversed, shift = off + T - 1), which is
+// the "full" correlation of the filtered-spectra gradient with the taps.
+#include "device_common.h"
+#include "launch.h"
+
+namespace pfb {
+
+template <int DT, int TP, int CPT, int D, bool REV>
+__global__ __launch_bounds__(256) void fir_kernel(FirArgs a)
+{
+    constexpr int U = TP > D ? TP : D; // outputs per unrolled step
+    static_assert(U % TP == 0 && U % D == 0, "unroll");
+    const int64_t nblocks = gridDim.x;
+    const int64_t lb = xcd_logical_block(blockIdx.x, nblocks);
+    const int64_t gw = lb * (blockDim.x >> 6) + wave_id();
+    const int64_t total = (int64_t)a.B * a.n_tiles * a.n_cchunks;
+    if (gw >= total)
+        return;
+    const int cch = (int)(gw % a.n_cchunks);
+    const int64_t rest = gw / a.n_cchunks;
+    const int tile = (int)(rest % a.n_tiles);
+    const int b = (int)(rest / a.n_tiles);
+
+    const int c0 = (cch * 64 + lane_id()) * CPT;
+    const bool active = c0 < a.C;
+    const int64_t s_begin = a.out_first + (int64_t)tile * a.SB;
+    const int64_t s_end = a.out_first + a.out_count;
+    const int nout = (int)((s_end - s_begin) < a.SB ? (s_end - s_begin) : a.SB);
+    const int64_t row0 = s_begin - a.shift; // input row of window slot 0
+    const int off = TP - a.T;
+
+    float hp[CPT][TP];
+#pragma unroll
+    for (int j = 0; j < TP; ++j) {
+        const int t = j - off;
+#pragma unroll
+        for (int k = 0; k < CPT; ++k)
+            hp[k][j] = (t >= 0 && active) ? a.h[(int64_t)(REV ? a.T - 1 - t : t) * a.C + c0 + k] : 0.0f;
+    }
+
+    const char *xb = reinterpret_cast<const char *>(a.x) + (int64_t)b * a.in_bstride * SampleBytes<DT>::value;
+    auto ld = [&](int64_t row, float2 (&o)[CPT]) {
+        if (active && row >= 0 && row < a.in_rows) {
+            Loader<DT, CPT>::load(xb, row * a.C + c0, o);
+        } else {
+#pragma unroll
+            for (int k = 0; k < CPT; ++k)
+                o[k] = make_float2(0.0f, 0.0f);
+        }
+    };
+
+    float2 w[TP][CPT];
+    float2 pf[D][CPT];
+#pragma unroll
+    for (int j = 0; j < TP - 1; ++j)
+        ld(row0 + j, w[j]);
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+        if (k < nout)
+            ld(row0 + TP - 1 + k, pf[k]);
+
+    float2 *yb = a.y + (int64_t)b * a.y_bstride + (s_begin - a.out_first) * a.C + c0;
+    for (int base = 0; base < nout; base += U) {
+#pragma unroll
+        for (int jj = 0; jj < U; ++jj) {
+            const int o = base + jj;
+            if (o < nout) {
+#pragma unroll
+                for (int k = 0; k < CPT; ++k)
+                    w[(jj + TP - 1) % TP][k] = pf[jj % D][k];
+                if (o + D < nout)
+                    ld(row0 + o + D + TP - 1, pf[jj % D]);
+                float2 acc[CPT];
+#pragma unroll
+                for (int k = 0; k < CPT; ++k) {
+                    float ar = 0.0f, ai = 0.0f;
+#pragma unroll
+                    for (int j = 0; j < TP; ++j) {
+                        ar = __builtin_fmaf(hp[k][j], w[(jj + j) % TP][k].x, ar);
+                        ai = __builtin_fmaf(hp[k][j], w[(jj + j) % TP][k].y, ai);
+                    }
+                    acc[k] = make_float2(ar, ai);
+                }
+                if (active)
+                    store_c64<CPT>(yb + (int64_t)o * a.C, acc);
+            }
+        }
+    }
+}
+
+// Tap gradient, first stage: per tile of filtered spectra and per channel,
+//   part[tile][t][c] = sum_{s in tile} Re(conj(gy[s][c]) x[s+t][c])
+// with the x window of the lane's channel kept in registers (TP rows).
+template <int TP, int D>
+__global__ __launch_bounds__(256) void gh_partial_kernel(GhArgs a)
+{
+    constexpr int U = TP > D ? TP : D;
+    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave_id();
+    const int64_t total = (int64_t)a.B * a.n_tiles * a.n_cchunks;
+    if (gw >= total)
+        return;
+    const int cch = (int)(gw % a.n_cchunks);
+    const int64_t rest = gw / a.n_cchunks;
+    const int tile = (int)(rest % a.n_tiles);
+    const int b = (int)(rest / a.n_tiles);
+    const int c = cch * 64 + lane_id();
+    const bool active = c < a.C;
+    const int64_t s_begin = (int64_t)tile * a.SB;
+    const int nout = (int)((a.S - s_begin) < a.SB ? (a.S - s_begin) : a.SB);
+    const int64_t in_rows = a.S + a.T - 1;
+    const float2 *xb = a.x + (int64_t)b * in_rows * a.C + c;
+    const float2 *gb = a.gy + (int64_t)b * a.S * a.C + c;
+
+    auto ldx = [&](int64_t row) -> float2 {
+        return (active && row < in_rows) ? xb[row * a.C] : make_float2(0.0f, 0.0f);
+    };
+    auto ldg = [&](int64_t s) -> float2 { return active ? gb[s * a.C] : make_float2(0.0f, 0.0f); };
+
+    float acc[TP];
+#pragma unroll
+    for (int j = 0; j < TP; ++j)
+        acc[j] = 0.0f;
+    float2 w[TP];
+    float2 pf[D];
+    float2 pg[D];
+#pragma unroll
+    for (int j = 0; j < TP - 1; ++j)
+        w[j] = ldx(s_begin + j);
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        if (k < nout) {
+            pf[k] = ldx(s_begin + TP - 1 + k);
+            pg[k] = ldg(s_begin + k);
+        }
+    }
+    for (int base = 0; base < nout; base += U) {
+#pragma unroll
+        for (int jj = 0; jj < U; ++jj) {
+            const int o = base + jj;
+            if (o < nout) {
+                w[(jj + TP - 1) % TP] = pf[jj % D];
+                const float2 g = pg[jj % D];
+                if (o + D < nout) {
+                    pf[jj % D] = ldx(s_begin + o + D + TP - 1);
+                    pg[jj % D] = ldg(s_begin + o + D);
+                }
+#pragma unroll
+                for (int j = 0; j < TP; ++j) {
+                    const float2 xv = w[(jj + j) % TP];
+                    acc[j] = __builtin_fmaf(g.x, xv.x, __builtin_fmaf(g.y, xv.y, acc[j]));
+                }
+            }
+        }
+    }
+    if (active) {
+        float *pb = a.part + ((int64_t)b * a.n_tiles + tile) * (int64_t)a.T * a.C + c;
+#pragma unroll
+        for (int j = 0; j < TP; ++j)
+            if (j < a.T)
+                pb[(int64_t)j * a.C] = acc[j];
+    }
+}
+
+// Tap gradient, second stage: gh[t][c] = sum over all tiles of the partials,
+// in ascending tile order (a fixed order, so the result is reproducible).
+__global__ __launch_bounds__(256) void gh_reduce_kernel(const float *__restrict__ part, float *__restrict__ gh,
+                                                        int64_t n_parts, int64_t tc)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= tc)
+        return;
+    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+    int64_t p = 0;
+    for (; p + 4 <= n_parts; p += 4) {
+        s0 += part[(p + 0) * tc + i];
+        s1 += part[(p + 1) * tc + i];
+        s2 += part[(p + 2) * tc + i];
+        s3 += part[(p + 3) * tc + i];
+    }
+    for (; p < n_parts; ++p)
+        s0 += part[p * tc + i];
+    gh[i] = (s0 + s1) + (s2 + s3);
+}
+
+// ----------------------------------------------------------------------------
+// Host launchers
+// ----------------------------------------------------------------------------
+
+template <int DT, int TP, int CPT, bool REV>
+static hipError_t launch_fir_t(const FirArgs &a, hipStream_t st)
+{
+    constexpr int D = TP >= 64 ? 8 : 16;
+    const int64_t total = (int64_t)a.B * a.n_tiles * a.n_cchunks;
+    const int64_t blocks = (total + 3) / 4;
+    if (blocks <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL((fir_kernel<DT, TP, CPT, D, REV>), dim3((unsigned)blocks), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int DT, bool REV>
+static hipError_t launch_fir_dt(const FirArgs &a, int tp, int cpt, hipStream_t st)
+{
+#define PFB_FIR_CASE(TPV)                                                                                    \
+    case TPV:                                                                                                \
+        return cpt == 2 ? launch_fir_t<DT, TPV, 2, REV>(a, st) : launch_fir_t<DT, TPV, 1, REV>(a, st);
+    switch (tp) {
+        PFB_FIR_CASE(4)
+        PFB_FIR_CASE(8)
+        PFB_FIR_CASE(16)
+        PFB_FIR_CASE(32)
+        PFB_FIR_CASE(64)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef PFB_FIR_CASE
+}
+
+hipError_t launch_fir(const FirArgs &a, int dtype, int tp, int cpt, bool rev, hipStream_t st)
+{
+    if (rev)
+        return dtype == DT_C64 ? launch_fir_dt<DT_C64, true>(a, tp, cpt, st) : hipErrorInvalidValue;
+    switch (dtype) {
+    case DT_C64:
+        return launch_fir_dt<DT_C64, false>(a, tp, cpt, st);
+    case DT_CI16:
+        return launch_fir_dt<DT_CI16, false>(a, tp, cpt, st);
+    case DT_CI8:
+        return launch_fir_dt<DT_CI8, false>(a, tp, cpt, st);
+    case DT_CF16:
+        return launch_fir_dt<DT_CF16, false>(a, tp, cpt, st);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+template <int TP> static hipError_t launch_gh_t(const GhArgs &a, hipStream_t st)
+{
+    constexpr int D = TP >= 64 ? 8 : 16;
+    const int64_t total = (int64_t)a.B * a.n_tiles * a.n_cchunks;
+    const int64_t blocks = (total + 3) / 4;
+    if (blocks <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL((gh_partial_kernel<TP, D>), dim3((unsigned)blocks), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_gh(const GhArgs &a, int tp, float *gh, hipStream_t st)
+{
+    hipError_t e;
+    switch (tp) {
+    case 4: e = launch_gh_t<4>(a, st); break;
+    case 8: e = launch_gh_t<8>(a, st); break;
+    case 16: e = launch_gh_t<16>(a, st); break;
+    case 32: e = launch_gh_t<32>(a, st); break;
+    case 64: e = launch_gh_t<64>(a, st); break;
+    default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess)
+        return e;
+    const int64_t tc = (int64_t)a.T * a.C;
+    const int64_t n_parts = (int64_t)a.B * a.n_tiles;
+    hipLaunchKernelGGL(gh_reduce_kernel, dim3((unsigned)((tc + 255) / 256)), dim3(256), 0, st, a.part, gh,
+                       n_parts, tc);
+    return hipGetLastError();
+}
+
+} // namespace pfb

@@ -1,0 +1,194 @@
+// Fused polyphase FIR + FFT (both steps of the Sec. 2 scheme in one pass).
+//
+// One workgroup of C/CPT threads owns every channel of a tile of S_B filtered
+// spectra of one stream (C in {256, 512, 1024}). Each thread keeps the last TP
+// raw samples of its CPT adjacent channels and their taps in registers (CPT
+// channels are loaded as one vector), so each raw sample
+// is read from HBM once per tile (Sec. 3.2 reuse principle) and converted to
+// float32 once. The tile is processed in chunks of RB filtered spectra:
+//   1. FIR: each thread produces RB filtered samples of its channel and
+//      writes them into an LDS row buffer [RB][C] (padded);
+//   2. FFT: the workgroup transforms the RB rows in LDS (one group of G lanes
+//      per row, Stockham passes through that row) and the last pass writes
+//      the frequency spectra straight to HBM, coalesced.
+// The filtered spectra never leave the chip, so the pass moves only the
+// input samples, the taps and the output spectra. Raw rows for the next chunk
+// are prefetched into registers before the transforms of the current chunk.
+#include "fft_device.h"
+#include "launch.h"
+
+namespace pfb {
+
+template <int LOG2C, int TP, int CPT> struct FusedShape {
+    static constexpr int C = 1 << LOG2C;
+    static constexpr int NT = C / CPT;               // threads per workgroup
+    using FL = FftLanes<LOG2C>;
+    static constexpr int G = FL::G;
+    static constexpr int NG = NT / G;                // rows transformed per round
+    static constexpr int RB = 16 > TP ? 16 : TP;     // filtered spectra per chunk
+    static constexpr int ROUNDS = RB / NG;
+    static constexpr int D = 8;                      // prefetch depth (rows)
+    using S = FftShape<LOG2C, G>;
+    static constexpr int LDS_BYTES = RB * S::PADDED * 8;
+    static_assert(NG >= 1 && RB % TP == 0 && RB % D == 0 && RB % NG == 0, "chunk shape");
+};
+
+// CPT used for each transform size: keeps the workgroup at <= 512 threads so
+// that a wave may hold up to 256 VGPRs (window, taps, prefetch and the
+// transform's 16 elements per lane) without spilling.
+constexpr int fused_cpt(int log2c) { return log2c >= 10 ? 2 : 1; }
+
+template <int DT, int TP, int LOG2C, int CPT>
+__global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_fwd_kernel(FusedArgs a)
+{
+    using F = FusedShape<LOG2C, TP, CPT>;
+    using S = typename F::S;
+    constexpr int C = F::C;
+    constexpr int RB = F::RB;
+    constexpr int D = F::D;
+    constexpr int G = F::G;
+    __shared__ float2 lds[RB * S::PADDED];
+
+    const int64_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int tile = (int)(lb % a.n_tiles);
+    const int b = (int)(lb / a.n_tiles);
+    const int t = (int)threadIdx.x;
+    const int c0 = t * CPT;
+    const int64_t s_begin = (int64_t)tile * a.SB;
+    const int nout = (int)((a.S - s_begin) < a.SB ? (a.S - s_begin) : a.SB);
+    const int off = TP - a.T;
+    const int64_t row0 = s_begin - off;
+    const int64_t in_rows = a.S + a.T - 1;
+
+    float hp[TP][CPT];
+#pragma unroll
+    for (int j = 0; j < TP; ++j)
+#pragma unroll
+        for (int k = 0; k < CPT; ++k)
+            hp[j][k] = (j >= off) ? a.h[(int64_t)(j - off) * C + c0 + k] : 0.0f;
+
+    const char *xb = reinterpret_cast<const char *>(a.x) + (int64_t)b * in_rows * C * SampleBytes<DT>::value;
+    auto ld = [&](int64_t row, float2 (&o)[CPT]) {
+        if (row >= 0 && row < in_rows) {
+            Loader<DT, CPT>::load(xb, row * C + c0, o);
+        } else {
+#pragma unroll
+            for (int k = 0; k < CPT; ++k)
+                o[k] = make_float2(0.0f, 0.0f);
+        }
+    };
+
+    float2 w[TP][CPT];
+    float2 pf[D][CPT];
+#pragma unroll
+    for (int j = 0; j < TP - 1; ++j)
+        ld(row0 + j, w[j]);
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+        if (k < nout)
+            ld(row0 + TP - 1 + k, pf[k]);
+
+    const int gid = t / G;
+    const int lane = t % G;
+    float2 *Yb = a.Y + ((int64_t)b * a.S + s_begin) * C;
+
+    for (int base = 0; base < nout; base += RB) {
+        // 1. FIR into the LDS row buffer
+#pragma unroll
+        for (int jj = 0; jj < RB; ++jj) {
+            const int o = base + jj;
+            if (o < nout) {
+#pragma unroll
+                for (int k = 0; k < CPT; ++k)
+                    w[(jj + TP - 1) % TP][k] = pf[jj % D][k];
+                if (o + D < nout)
+                    ld(row0 + o + D + TP - 1, pf[jj % D]);
+#pragma unroll
+                for (int k = 0; k < CPT; ++k) {
+                    float ar = 0.0f, ai = 0.0f;
+#pragma unroll
+                    for (int j = 0; j < TP; ++j) {
+                        ar = __builtin_fmaf(hp[j][k], w[(jj + j) % TP][k].x, ar);
+                        ai = __builtin_fmaf(hp[j][k], w[(jj + j) % TP][k].y, ai);
+                    }
+                    lds[jj * S::PADDED + S::pad(c0 + k)] = make_float2(ar, ai);
+                }
+            }
+        }
+        __syncthreads();
+        // 2. FFT of the chunk's rows, straight to HBM
+#pragma unroll 1
+        for (int round = 0; round < F::ROUNDS; ++round) {
+            const int r = round * F::NG + gid;
+            const bool valid = base + r < nout;
+            float2 *row = lds + r * S::PADDED;
+            float2 *out = Yb + (int64_t)(base + r) * C;
+            fft_run<LOG2C, G, false, true>(
+                lane, row, a.tw, [&](int idx) { return row[S::pad(idx)]; },
+                [&](int idx, float2 v) {
+                    if (valid)
+                        out[idx] = v;
+                });
+        }
+        __syncthreads();
+    }
+}
+
+bool fused_supported(int dtype, int tp, int log2c)
+{
+    if (dtype < 0 || dtype > 3)
+        return false;
+    if (log2c < 8 || log2c > 10)
+        return false;
+    return tp == 4 || tp == 8 || tp == 16;
+}
+
+int fused_rows_per_chunk(int tp, int log2c)
+{
+    (void)log2c;
+    return 16 > tp ? 16 : tp;
+}
+
+template <int DT, int TP, int LOG2C> static hipError_t launch_fused_t(const FusedArgs &a, hipStream_t st)
+{
+    const int64_t blocks = (int64_t)a.B * a.n_tiles;
+    if (blocks <= 0)
+        return hipSuccess;
+    constexpr int CPT = fused_cpt(LOG2C);
+    hipLaunchKernelGGL((fused_fwd_kernel<DT, TP, LOG2C, CPT>), dim3((unsigned)blocks), dim3((1 << LOG2C) / CPT), 0,
+                       st, a);
+    return hipGetLastError();
+}
+
+template <int DT> static hipError_t launch_fused_dt(const FusedArgs &a, int tp, int log2c, hipStream_t st)
+{
+#define PFB_FUSED_C(L2)                                                                                      \
+    case L2:                                                                                                 \
+        switch (tp) {                                                                                        \
+        case 4: return launch_fused_t<DT, 4, L2>(a, st);                                                     \
+        case 8: return launch_fused_t<DT, 8, L2>(a, st);                                                     \
+        case 16: return launch_fused_t<DT, 16, L2>(a, st);                                                   \
+        default: return hipErrorInvalidValue;                                                                \
+        }
+    switch (log2c) {
+        PFB_FUSED_C(8)
+        PFB_FUSED_C(9)
+        PFB_FUSED_C(10)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef PFB_FUSED_C
+}
+
+hipError_t launch_fused(const FusedArgs &a, int dtype, int tp, int log2c, hipStream_t st)
+{
+    switch (dtype) {
+    case DT_C64: return launch_fused_dt<DT_C64>(a, tp, log2c, st);
+    case DT_CI16: return launch_fused_dt<DT_CI16>(a, tp, log2c, st);
+    case DT_CI8: return launch_fused_dt<DT_CI8>(a, tp, log2c, st);
+    case DT_CF16: return launch_fused_dt<DT_CF16>(a, tp, log2c, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+} // namespace pfb

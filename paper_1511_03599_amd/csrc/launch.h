@@ -1,0 +1,69 @@
+// Internal launch interface between the C ABI (api.hip) and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pfb {
+
+// FIR launch over output rows [out_first, out_first + out_count) of each of B
+// streams. Output row s of stream b goes to y + b*y_bstride + (s - out_first)*C.
+struct FirArgs {
+    const void *x;       // stream 0, row 0
+    const float *h;      // taps [T][C]
+    float2 *y;
+    int C, T, B;
+    int SB;              // output rows per tile
+    int n_tiles;         // tiles per stream
+    int n_cchunks;       // channel chunks of 64*CPT
+    int64_t in_rows;     // rows readable per stream; others read as zero
+    int64_t in_bstride;  // samples between streams in x
+    int64_t shift;       // window slot 0 of output s reads input row s - shift
+    int64_t out_first;
+    int64_t out_count;
+    int64_t y_bstride;   // complex values between streams in y
+};
+
+// Tap-gradient partials over tiles of S_B filtered spectra.
+struct GhArgs {
+    const float2 *x;     // [B][S+T-1][C]
+    const float2 *gy;    // [B][S][C]
+    float *part;         // [B*n_tiles][T][C]
+    int C, T, B;
+    int SB, n_tiles, n_cchunks;
+    int64_t S;
+};
+
+// Batched C-point transforms of `nrows` rows. Row r lives at
+// in + (r / rows_per_group)*in_gstride + (r % rows_per_group)*C, and likewise
+// for out.
+struct FftArgs {
+    const float2 *in;
+    float2 *out;
+    const float2 *tw;    // C twiddles exp(-2 pi i n / C)
+    int64_t nrows;
+    int64_t rows_per_group;
+    int64_t in_gstride;
+    int64_t out_gstride;
+};
+
+// Fused FIR + FFT: one workgroup holds all C channels of a tile of S_B
+// filtered spectra of one stream.
+struct FusedArgs {
+    const void *x;       // [B][S+T-1][C]
+    const float *h;      // [T][C]
+    float2 *Y;           // [B][S][C]
+    const float2 *tw;
+    int T, B;
+    int SB, n_tiles;
+    int64_t S;
+};
+
+hipError_t launch_fir(const FirArgs &a, int dtype, int tp, int cpt, bool rev, hipStream_t st);
+hipError_t launch_gh(const GhArgs &a, int tp, float *gh, hipStream_t st);
+hipError_t launch_fft(const FftArgs &a, int log2c, bool inv, hipStream_t st);
+hipError_t launch_fused(const FusedArgs &a, int dtype, int tp, int log2c, hipStream_t st);
+bool fused_supported(int dtype, int tp, int log2c);
+int fused_rows_per_chunk(int tp, int log2c);
+
+} // namespace pfb

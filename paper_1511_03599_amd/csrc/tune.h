@@ -1,0 +1,32 @@
+// Internal declarations shared by the C-ABI translation units: the tuning
+// cache and the batched-plan module.
+#pragma once
+
+#include "../../include/pfb.h"
+
+namespace pfb {
+
+// One tuned configuration for a descriptor (arch, dtype, C, T, flags class).
+struct TuneEntry {
+    int path = -1;       // 0 fused, 1 split, -1 not set
+    int fir_cpt = 0;     // FIR channels per thread
+    int fir_sb = 0;      // FIR rows per tile
+    int fused_sb = 0;    // fused rows per tile
+    int chunk_mib = 0;   // split-path chunk size
+};
+
+// Look the descriptor up in the cache file named by PFB_TUNE_CACHE. Returns
+// false (and leaves *out untouched) when the variable is unset, the file is
+// missing or unreadable, or has no entry for this descriptor.
+bool tune_lookup(const pfb_desc &d, TuneEntry *out);
+
+} // namespace pfb
+
+struct Batched;
+void batched_free(Batched *b);
+
+pfb_status pfb_internal_fail(pfb_status st, const char *msg);
+pfb_status pfb_internal_validate(const pfb_desc *d, bool batched_beam);
+pfb_plan *pfb_internal_new_plan();
+void pfb_internal_set_batched(pfb_plan *p, Batched *b);
+Batched *pfb_internal_get_batched(pfb_plan *p);

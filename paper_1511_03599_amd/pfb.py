@@ -1,0 +1,232 @@
+"""Python binding of libpfb.so (the C ABI in include/pfb.h).
+
+Argument marshalling only: tensors are passed to the library as device
+pointers together with torch's current HIP stream, and every step of the
+computation runs in the library's kernels. There is no fallback: if the
+library is missing or a call fails, a PFBError is raised.
+
+Tensor conventions (all on the GPU, contiguous):
+  x   [B, S+T-1, C] complex64, or [B, S+T-1, C, 2] int16 / int8 / float16
+  h   [T, C] float32
+  Y   [B, S, C] complex64 (frequency spectra), y likewise (filtered spectra)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpfb.so")
+
+# pfb_status
+PFB_OK, PFB_E_INVALID, PFB_E_UNSUPPORTED, PFB_E_NOMEM, PFB_E_HIP, PFB_E_STATE = range(6)
+# pfb_dtype
+DTYPE_CODES = {"c64": 0, "ci16": 1, "ci8": 2, "cf16": 3}
+# flags
+FIR_ONLY, NO_FUSE, PLAIN = 1, 4, 8
+PATH_NAMES = {0: "fused", 1: "split", 2: "fir_only"}
+MAX_TAPS = 64
+
+
+class PFBError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("channels", ctypes.c_int32), ("taps", ctypes.c_int32), ("spectra", ctypes.c_int64),
+                ("batch", ctypes.c_int32), ("dtype", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_int32), ("fir_rows", ctypes.c_int32), ("fir_cpt", ctypes.c_int32),
+                ("padded_taps", ctypes.c_int32), ("workspace_bytes", ctypes.c_int64),
+                ("chunk_rows", ctypes.c_int64)]
+
+
+EXPORTED = ("pfb_plan_create", "pfb_execute", "pfb_backward", "pfb_plan_create_batched",
+            "pfb_execute_batched", "pfb_tune", "pfb_plan_get_info", "pfb_plan_destroy",
+            "pfb_status_str", "pfb_last_error")
+
+_lib = None
+
+
+def lib():
+    """Load libpfb.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise PFBError(PFB_E_STATE, f"{LIB_PATH} is missing: build it with "
+                                    "`python -m paper_1511_03599_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, st = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int
+    L.pfb_plan_create.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(vp)]
+    L.pfb_execute.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.pfb_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.pfb_plan_create_batched.argtypes = [i32, ctypes.POINTER(Desc), ctypes.POINTER(vp)]
+    L.pfb_execute_batched.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
+    L.pfb_tune.argtypes = [ctypes.POINTER(Desc), ctypes.c_char_p]
+    L.pfb_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+    L.pfb_plan_destroy.argtypes = [vp]
+    L.pfb_status_str.argtypes = [st]
+    L.pfb_status_str.restype = ctypes.c_char_p
+    L.pfb_last_error.argtypes = []
+    L.pfb_last_error.restype = ctypes.c_char_p
+    for f in ("pfb_plan_create", "pfb_execute", "pfb_backward", "pfb_plan_create_batched",
+              "pfb_execute_batched", "pfb_tune", "pfb_plan_get_info", "pfb_plan_destroy"):
+        getattr(L, f).restype = st
+    _lib = L
+    return L
+
+
+def check(status: int):
+    if status != PFB_OK:
+        msg = lib().pfb_last_error().decode(errors="replace")
+        raise PFBError(status, msg or lib().pfb_status_str(status).decode())
+
+
+def make_desc(channels, taps, spectra, batch=1, dtype="c64", flags=0) -> Desc:
+    return Desc(int(channels), int(taps), int(spectra), int(batch), DTYPE_CODES[dtype], int(flags))
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def dtype_of(x: torch.Tensor) -> str:
+    if x.dtype == torch.complex64:
+        return "c64"
+    if x.dtype == torch.float32 and x.shape[-1] == 2:
+        return "c64"
+    return {torch.int16: "ci16", torch.int8: "ci8", torch.float16: "cf16"}[x.dtype]
+
+
+class Plan:
+    """One filter-bank problem: B streams of S filtered spectra, C channels,
+    T taps, input element type `dtype`."""
+
+    def __init__(self, channels, taps, spectra, batch=1, dtype="c64", flags=0):
+        self.C, self.T, self.S, self.B = int(channels), int(taps), int(spectra), int(batch)
+        self.dtype, self.flags = dtype, int(flags)
+        d = make_desc(channels, taps, spectra, batch, dtype, flags)
+        h = ctypes.c_void_p()
+        check(lib().pfb_plan_create(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def rows(self):
+        return self.S + self.T - 1
+
+    def info(self) -> dict:
+        i = PlanInfo()
+        check(lib().pfb_plan_get_info(self._h, ctypes.byref(i)))
+        return {"path": PATH_NAMES.get(i.path, i.path), "fir_rows": i.fir_rows, "fir_cpt": i.fir_cpt,
+                "padded_taps": i.padded_taps, "workspace_bytes": i.workspace_bytes,
+                "chunk_rows": i.chunk_rows}
+
+    def _check_x(self, x):
+        want = (self.B, self.rows, self.C)
+        shp = tuple(x.shape[:3]) if x.dim() >= 3 else None
+        if not x.is_cuda or shp != want or not x.is_contiguous():
+            raise PFBError(PFB_E_INVALID, f"x must be a contiguous CUDA tensor of shape {want}(+2)")
+        if dtype_of(x) != self.dtype:
+            raise PFBError(PFB_E_INVALID, f"x dtype {x.dtype} does not match plan dtype {self.dtype}")
+
+    def _check_h(self, h):
+        if not h.is_cuda or h.dtype != torch.float32 or tuple(h.shape) != (self.T, self.C) \
+                or not h.is_contiguous():
+            raise PFBError(PFB_E_INVALID, f"taps must be contiguous float32 CUDA [{self.T}, {self.C}]")
+
+    def execute(self, x, h, Y=None, y=None, stream=None):
+        """Forward pass. Returns Y (or y for a FIR-only plan)."""
+        self._check_x(x)
+        self._check_h(h)
+        out_shape = (self.B, self.S, self.C)
+        if self.flags & FIR_ONLY:
+            if y is None:
+                y = torch.empty(out_shape, dtype=torch.complex64, device=x.device)
+            check(lib().pfb_execute(self._h, _ptr(x), _ptr(h), _ptr(y), None, _stream(stream)))
+            return y
+        if Y is None:
+            Y = torch.empty(out_shape, dtype=torch.complex64, device=x.device)
+        check(lib().pfb_execute(self._h, _ptr(x), _ptr(h), _ptr(y), _ptr(Y), _stream(stream)))
+        return Y
+
+    def backward(self, x, h, gY, gx=None, gh=None, want_gx=True, want_gh=True, stream=None):
+        """Adjoint pass for a real loss with frequency-spectra gradient gY.
+        Returns (gx, gh); either is None when not requested."""
+        self._check_h(h)
+        if want_gh or x is not None:
+            self._check_x(x)
+        if gY.dtype != torch.complex64 or tuple(gY.shape) != (self.B, self.S, self.C) \
+                or not gY.is_contiguous():
+            raise PFBError(PFB_E_INVALID, "gY must be contiguous complex64 [B, S, C]")
+        if want_gx and gx is None:
+            gx = torch.empty((self.B, self.rows, self.C), dtype=torch.complex64, device=gY.device)
+        if want_gh and gh is None:
+            gh = torch.empty((self.T, self.C), dtype=torch.float32, device=gY.device)
+        check(lib().pfb_backward(self._h, _ptr(x), _ptr(h), _ptr(gY), _ptr(gx if want_gx else None),
+                                 _ptr(gh if want_gh else None), _stream(stream)))
+        return (gx if want_gx else None), (gh if want_gh else None)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pfb_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_plan_cache: dict = {}
+
+
+def cached_plan(C, T, S, B=1, dtype="c64", flags=0) -> Plan:
+    key = (C, T, S, B, dtype, flags, torch.cuda.current_device())
+    p = _plan_cache.get(key)
+    if p is None:
+        p = Plan(C, T, S, B, dtype, flags)
+        _plan_cache[key] = p
+    return p
+
+
+class PFBFunction(torch.autograd.Function):
+    """Y = PFB(x, h) with the library's hand-written adjoint as backward.
+    x: complex64 [B, S+T-1, C]; h: float32 [T, C]; Y: complex64 [B, S, C].
+    Gradients follow torch's complex convention (dL/dRe + i dL/dIm)."""
+
+    @staticmethod
+    def forward(ctx, x, h):
+        B, rows, C = x.shape
+        T = h.shape[0]
+        plan = cached_plan(C, T, rows - T + 1, B, "c64", 0)
+        x = x.contiguous()
+        h = h.contiguous()
+        Y = plan.execute(x, h)
+        ctx.save_for_backward(x, h)
+        ctx.plan = plan
+        return Y
+
+    @staticmethod
+    def backward(ctx, gY):
+        x, h = ctx.saved_tensors
+        need_x, need_h = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+        gx, gh = ctx.plan.backward(x, h, gY.contiguous(), want_gx=need_x, want_gh=need_h)
+        return gx, gh
+
+
+def pfb(x, h):
+    return PFBFunction.apply(x, h)

@@ -206,14 +206,17 @@ def tone_params(B: int, C: int, seed: int):
 
 def tone_streams(B=32, C=1024, T=16, S=8192, seed=None) -> Stream:
     """Differentiable workload: per stream a unit tone at (k_b + delta_b)/C
-    cycles per sample, tone only, complex64."""
+    cycles per sample, tone only, complex64 (generated per stream in float64
+    and rounded once)."""
     seed = seed_for(5) if seed is None else seed
     rows = S + T - 1
     k, d, ph = tone_params(B, C, seed)
-    xc = np.empty((B, rows, C), dtype=np.complex128)
+    x = np.empty((B, rows, C, 2), dtype=np.float32)
     for b in range(B):
-        xc[b] = offset_tone(rows, C, (k[b] + d[b]) / C, ph[b])
-    st = Stream(quantise(xc, "c64"), windowed_sinc_taps(C, T), "c64", B, S, C, T)
+        xb = offset_tone(rows, C, (k[b] + d[b]) / C, ph[b])
+        x[b, ..., 0] = xb.real
+        x[b, ..., 1] = xb.imag
+    st = Stream(x, windowed_sinc_taps(C, T), "c64", B, S, C, T)
     st.tone_bins = k
     return st
 

@@ -1,0 +1,196 @@
+"""GPU parity of the forward filter bank against the FP64 oracle, through the
+C ABI (ctypes binding). Tolerances: relative L2 <= 2e-6 for the filtered
+spectra and <= 1e-5 for the frequency spectra, per stream."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1511_03599_amd import synth
+from helpers import FIR_TOL, SPEC_TOL, c128, rel_l2, rel_l2_per_stream, say, taps_to_device, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+def pfbmod():
+    from paper_1511_03599_amd import pfb
+    return pfb
+
+
+def make(C, T, S, B, dtype, seed, taps="random"):
+    st = synth.noise_stream(B, C, T, S, seed, dtype=dtype)
+    h = synth.random_taps(C, T, seed + 7) if taps == "random" else st.h
+    return st.x, h
+
+
+@pytest.mark.parametrize("C,T,S,B,dtype", [
+    (1, 4, 50, 1, "c64"), (3, 5, 37, 2, "c64"), (100, 16, 300, 2, "c64"), (1024, 8, 520, 1, "c64"),
+    (256, 1, 20, 1, "c64"), (64, 64, 200, 1, "c64"), (96, 33, 130, 1, "c64"), (1000, 2, 9, 3, "c64"),
+    (130, 17, 260, 1, "ci16"), (4096, 16, 40, 1, "ci8"), (512, 32, 300, 1, "cf16"), (77, 7, 77, 2, "ci8"),
+])
+def test_fir_only_parity(dev, C, T, S, B, dtype):
+    pfb = pfbmod()
+    say(f"fir_only C={C} T={T} S={S} B={B} {dtype}")
+    x, h = make(C, T, S, B, dtype, 100 + C + T)
+    plan = pfb.Plan(C, T, S, B, dtype, pfb.FIR_ONLY)
+    y = plan.execute(to_device(x, dev), taps_to_device(h, dev))
+    ref = oracle.fir(x, h)
+    errs = rel_l2_per_stream(c128(y), ref)
+    assert max(errs) <= FIR_TOL, errs
+
+
+FWD_CASES = [(C, T) for C in (32, 64, 128, 256, 512, 1024, 2048, 4096, 8192) for T in (4, 8, 16)]
+
+
+def rows_for(C):
+    return max(3, min(300, int(6e7 // (C * C))))
+
+
+@pytest.mark.parametrize("C,T", FWD_CASES)
+@pytest.mark.parametrize("mode", ["default", "split", "plain"])
+def test_forward_parity_c64(dev, C, T, mode):
+    pfb = pfbmod()
+    S, B = rows_for(C) + 1, 2
+    flags = {"default": 0, "split": pfb.NO_FUSE, "plain": pfb.PLAIN}[mode]
+    say(f"forward C={C} T={T} S={S} B={B} mode={mode}")
+    x, h = make(C, T, S, B, "c64", 200 + C + T)
+    plan = pfb.Plan(C, T, S, B, "c64", flags)
+    info = plan.info()
+    if mode != "default":
+        assert info["path"] == "split"
+    Y = plan.execute(to_device(x, dev), taps_to_device(h, dev))
+    ref = oracle.pfb_forward(x, h)
+    errs = rel_l2_per_stream(c128(Y), ref)
+    assert max(errs) <= SPEC_TOL, (info, errs)
+
+
+@pytest.mark.parametrize("C,T", [(256, 8), (1024, 16), (4096, 4), (32, 16)])
+def test_forward_with_filtered_output(dev, C, T):
+    """Asking for y as well runs FIR then FFT and returns both."""
+    import torch
+    pfb = pfbmod()
+    S = rows_for(C)
+    x, h = make(C, T, S, 1, "c64", 300 + C)
+    plan = pfb.Plan(C, T, S, 1, "c64")
+    y = torch.empty((1, S, C), dtype=torch.complex64, device=dev)
+    Y = plan.execute(to_device(x, dev), taps_to_device(h, dev), y=y)
+    Yr, yr = oracle.pfb_forward(x, h, want_y=True)
+    assert rel_l2(c128(y), yr) <= FIR_TOL
+    assert rel_l2(c128(Y), Yr) <= SPEC_TOL
+
+
+@pytest.mark.parametrize("dtype", ["ci8", "ci16", "cf16"])
+@pytest.mark.parametrize("C,T", [(256, 16), (1024, 16), (1024, 4), (4096, 16), (128, 8)])
+def test_forward_parity_low_precision(dev, dtype, C, T):
+    pfb = pfbmod()
+    S = rows_for(C)
+    say(f"forward {dtype} C={C} T={T} S={S}")
+    x, h = make(C, T, S, 1, dtype, 400 + C + T, taps="sinc")
+    plan = pfb.Plan(C, T, S, 1, dtype)
+    Y = plan.execute(to_device(x, dev), taps_to_device(h, dev))
+    ref = oracle.pfb_forward(x, h)
+    assert rel_l2(c128(Y), ref) <= SPEC_TOL, plan.info()
+
+
+@pytest.mark.parametrize("mode", ["fir_only", "split_y"])
+@pytest.mark.parametrize("T", [1, 3, 8, 16, 37, 64])
+def test_impulse_gives_reversed_taps_bit_exact(dev, mode, T):
+    import torch
+    pfb = pfbmod()
+    C, S = 256, T + 5
+    h = synth.random_taps(C, T, 17)
+    x = np.zeros((1, S + T - 1, C, 2), dtype=np.float32)
+    x[0, T - 1, :, 0] = 1.0
+    xd = to_device(x, dev)
+    if mode == "fir_only":
+        y = pfb.Plan(C, T, S, 1, "c64", pfb.FIR_ONLY).execute(xd, taps_to_device(h, dev))
+    else:
+        y = torch.empty((1, S, C), dtype=torch.complex64, device=dev)
+        pfb.Plan(C, T, S, 1, "c64").execute(xd, taps_to_device(h, dev), y=y)
+    y = y.cpu().numpy()
+    for s in range(S):
+        want = h[T - 1 - s] if s < T else np.zeros(C, np.float32)
+        assert np.array_equal(y[0, s].real, want), s
+        assert np.array_equal(y[0, s].imag, np.zeros(C, np.float32)), s
+
+
+@pytest.mark.parametrize("C,T,flags", [(1024, 16, 0), (1024, 16, 4), (512, 8, 0), (4096, 8, 0), (128, 4, 0),
+                                       (256, 33, 0)])
+def test_shift_equivariance_bit_exact(dev, C, T, flags):
+    """Dropping the first raw spectrum shifts y and Y by one spectrum, bit for
+    bit (catches halo and tile-edge mistakes)."""
+    pfb = pfbmod()
+    S = 150
+    x, h = make(C, T, S, 1, "c64", 500 + C)
+    hd = taps_to_device(h, dev)
+    xd = to_device(x, dev)
+    Y = pfb.Plan(C, T, S, 1, "c64", flags).execute(xd, hd).cpu().numpy()
+    Y2 = pfb.Plan(C, T, S - 1, 1, "c64", flags).execute(xd[:, 1:].contiguous(), hd).cpu().numpy()
+    assert np.array_equal(Y2[0], Y[0, 1:])
+
+
+def test_repeat_runs_bit_identical(dev):
+    pfb = pfbmod()
+    C, T, S, B = 1024, 16, 700, 2
+    x, h = make(C, T, S, B, "c64", 600)
+    plan = pfb.Plan(C, T, S, B, "c64")
+    xd, hd = to_device(x, dev), taps_to_device(h, dev)
+    a = plan.execute(xd, hd).cpu().numpy()
+    b = plan.execute(xd, hd).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_tone_in_channel_37(dev):
+    """Single stream, C=256, T=8, 4096 spectra: noise plus a unit tone at the
+    centre of channel 37 peaks in bin 37 in every spectrum."""
+    pfb = pfbmod()
+    st = synth.small_stream()
+    plan = pfb.Plan(st.C, st.T, st.S, 1, "c64")
+    Y = c128(plan.execute(to_device(st.x, dev), taps_to_device(st.h, dev)))
+    assert np.all(np.argmax(np.abs(Y[0]), axis=-1) == 37)
+    ref = oracle.pfb_forward(st.x, st.h)
+    assert rel_l2(Y, ref) <= SPEC_TOL
+
+
+def test_all_dtypes_agree_on_exact_integer_input(dev):
+    """Integer-valued input stored exactly in every dtype gives the same
+    spectra bit for bit: the conversion at load is exact."""
+    pfb = pfbmod()
+    C, T, S = 1024, 16, 64
+    g = synth.rng(9)
+    xi = g.integers(-100, 101, size=(1, S + T - 1, C, 2))
+    h = synth.random_taps(C, T, 10)
+    hd = taps_to_device(h, dev)
+    outs = []
+    for dt, npdt in (("c64", np.float32), ("ci16", np.int16), ("ci8", np.int8), ("cf16", np.float16)):
+        Y = pfb.Plan(C, T, S, 1, dt).execute(to_device(xi.astype(npdt), dev), hd)
+        outs.append(Y.cpu().numpy())
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+@pytest.mark.parametrize("T", [4, 8, 16, 32, 64])
+def test_full_size_sweep_sampled(dev, T):
+    """C=1024, 65536 filtered spectra (the tap-sweep workload) at full size:
+    FIR-only and FIR+FFT checked on sampled spectra, including the first and
+    last and the ones either side of tile edges."""
+    import torch
+    pfb = pfbmod()
+    C, S = 1024, 65536
+    say(f"full size T={T}")
+    st = synth.noise_stream(1, C, T, S, synth.seed_for(2, T), fast=True)
+    xd = to_device(st.x, dev)
+    hd = taps_to_device(st.h, dev)
+    plan_f = pfb.Plan(C, T, S, 1, "c64", pfb.FIR_ONLY)
+    y = plan_f.execute(xd, hd)
+    plan = pfb.Plan(C, T, S, 1, "c64")
+    Y = plan.execute(xd, hd)
+    torch.cuda.synchronize()
+    g = synth.rng(T)
+    rows = sorted(set([0, 1, 15, 16, 255, 256, 257, S // 2, S - 2, S - 1] + list(g.integers(0, S, 6))))
+    sel = torch.tensor(rows, device=dev)
+    ys = c128(y[0].index_select(0, sel))
+    Ys = c128(Y[0].index_select(0, sel))
+    for i, s in enumerate(rows):
+        Yr, yr = oracle.pfb_forward(st.x[:, s:s + T], st.h, want_y=True)
+        assert rel_l2(ys[i], yr[0, 0]) <= FIR_TOL, (s, plan_f.info())
+        assert rel_l2(Ys[i], Yr[0, 0]) <= SPEC_TOL, (s, plan.info())
