@@ -108,6 +108,8 @@ typedef struct {
     int32_t padded_taps;   /* taps rounded up to the kernel's template size    */
     int64_t workspace_bytes;
     int64_t chunk_rows;    /* spectra per FIR/FFT chunk on the split path      */
+    int32_t backward_fused;/* 1 if pfb_backward runs the fused adjoint kernel  */
+    int32_t reserved;
 } pfb_plan_info;
 
 /*

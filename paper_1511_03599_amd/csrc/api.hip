@@ -105,6 +105,8 @@ struct pfb_plan {
     float *ws_gh = nullptr;      // backward: tap-gradient partials
     int64_t ws_gh_bytes = 0;
     int gh_sb = 256;
+    bool bwd_fused = false;      // fused adjoint kernel
+    int bwd_sb = 256;            // gx rows per fused adjoint tile
     // batched
     struct Batched *batched = nullptr;
 };
@@ -210,19 +212,14 @@ static pfb_status dev_alloc(void **p, int64_t bytes, const char *what)
 
 static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// Rows per fused tile: about one tile per CU in a single wave of tiles for
-// the whole job, a multiple of the chunk height, at least one chunk.
+// Rows per fused tile: short tiles (four chunks) so that many workgroups
+// run in launch order and the resident ones sweep a narrow band of rows; the
+// halo rows they share with the previous tile are then still cached.
 static int choose_fused_sb(const pfb_desc &d, int rb)
 {
-    const int64_t total = (int64_t)d.batch * d.spectra;
-    int64_t sb = ceil_div(total, 256);
-    sb = ceil_div(sb, rb) * rb;
+    int64_t sb = 4 * (int64_t)rb;
     if (sb > d.spectra)
         sb = ceil_div(d.spectra, rb) * rb;
-    if (sb < rb)
-        sb = rb;
-    if (sb > 8192)
-        sb = 8192;
     return (int)sb;
 }
 
@@ -237,15 +234,21 @@ static pfb_status plan_single(const pfb_desc *d, pfb_plan *p)
 
     TuneEntry te;
     const bool tuned = tune_lookup(*d, &te);
-    p->fir_cpt = (d->channels % 2 == 0) ? 2 : 1;
-    p->fir_sb = 256;
+    // Two channels per lane (16-byte complex64 loads) where the doubled
+    // register window fits (padded taps <= 16) and C is even; short tiles of
+    // 32 filtered spectra keep many waves resident (the halo rows they re-read
+    // are served by the caches).
+    const bool cpt2_ok = p->tp <= 16 && d->channels % 2 == 0;
+    p->fir_cpt = cpt2_ok ? 2 : 1;
+    p->fir_sb = p->tp >= 64 ? 64 : 32;
     if (tuned) {
-        if (te.fir_cpt == 1 || (te.fir_cpt == 2 && d->channels % 2 == 0))
+        if (te.fir_cpt == 1 || (te.fir_cpt == 2 && cpt2_ok))
             p->fir_cpt = te.fir_cpt;
         if (te.fir_sb >= 16 && te.fir_sb <= 8192)
             p->fir_sb = te.fir_sb;
     }
     if (d->flags & PFB_PLAIN) {
+        // the untuned comparator: one channel per lane, long tiles
         p->fir_cpt = 1;
         p->fir_sb = 256;
     }
@@ -289,13 +292,20 @@ static pfb_status plan_single(const pfb_desc *d, pfb_plan *p)
         if (st != PFB_OK)
             return st;
         if (d->dtype == PFB_C64) {
-            p->ws_gy_bytes = (int64_t)d->batch * d->spectra * row_bytes;
-            st = dev_alloc(reinterpret_cast<void **>(&p->ws_gy), p->ws_gy_bytes, "backward workspace");
-            if (st != PFB_OK)
-                return st;
-            p->gh_sb = 256;
-            const int64_t n_tiles = ceil_div(d->spectra, p->gh_sb);
-            p->ws_gh_bytes = (int64_t)d->batch * n_tiles * d->taps * d->channels * 4;
+            p->bwd_fused = !(d->flags & (PFB_NO_FUSE | PFB_PLAIN)) && fused_bwd_supported(p->tp, p->log2c);
+            if (tuned && te.bwd_sb >= 16 && te.bwd_sb <= 65536)
+                p->bwd_sb = te.bwd_sb;
+            int64_t parts;
+            if (p->bwd_fused) {
+                parts = (int64_t)d->batch * ceil_div(d->spectra + d->taps - 1, p->bwd_sb);
+            } else {
+                p->ws_gy_bytes = (int64_t)d->batch * d->spectra * row_bytes;
+                st = dev_alloc(reinterpret_cast<void **>(&p->ws_gy), p->ws_gy_bytes, "backward workspace");
+                if (st != PFB_OK)
+                    return st;
+                parts = (int64_t)d->batch * ceil_div(d->spectra, p->gh_sb);
+            }
+            p->ws_gh_bytes = parts * d->taps * d->channels * 4;
             st = dev_alloc(reinterpret_cast<void **>(&p->ws_gh), p->ws_gh_bytes, "tap-gradient partials");
             if (st != PFB_OK)
                 return st;
@@ -336,6 +346,7 @@ extern "C" pfb_status pfb_plan_get_info(const pfb_plan *p, pfb_plan_info *info)
     info->fir_cpt = p->fir_cpt;
     info->padded_taps = p->tp;
     info->workspace_bytes = p->ws_y_bytes + p->ws_gy_bytes + p->ws_gh_bytes;
+    info->backward_fused = p->bwd_fused ? 1 : 0;
     info->chunk_rows = p->chunk_rows;
     return PFB_OK;
 }
@@ -469,6 +480,24 @@ extern "C" pfb_status pfb_backward(pfb_plan *p, const void *x, const float *taps
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const int64_t C = d.channels, S = d.spectra, T = d.taps;
     hipError_t e;
+    if (p->bwd_fused) {
+        BwdArgs a{};
+        a.x = reinterpret_cast<const float2 *>(x);
+        a.h = taps;
+        a.gY = reinterpret_cast<const float2 *>(gY);
+        a.gx = reinterpret_cast<float2 *>(gx);
+        a.part = gh ? p->ws_gh : nullptr;
+        a.tw = p->twiddle;
+        a.T = d.taps;
+        a.B = d.batch;
+        a.SB = p->bwd_sb;
+        a.n_tiles = (int)ceil_div(S + T - 1, a.SB);
+        a.S = S;
+        e = launch_fused_bwd(a, p->tp, p->log2c, st);
+        if (e == hipSuccess && gh)
+            e = launch_gh_reduce(p->ws_gh, gh, (int64_t)d.batch * a.n_tiles, T * C, st);
+        return e == hipSuccess ? PFB_OK : hip_fail(e, "fused adjoint launch");
+    }
     // 1. gy = unnormalised inverse DFT of gY (adjoint of Eq. (2))
     e = run_fft(p, reinterpret_cast<const float2 *>(gY), p->ws_gy, (int64_t)d.batch * S, S, S * C, S * C, true, st);
     if (e != hipSuccess)

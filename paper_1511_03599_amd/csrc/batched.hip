@@ -29,9 +29,3 @@ extern "C" pfb_status pfb_execute_batched(pfb_plan *p, const void *const *x, con
     return pfb_internal_fail(PFB_E_UNSUPPORTED, "batched plans are not built yet");
 }
 
-extern "C" pfb_status pfb_tune(const pfb_desc *desc, const char *cache_path)
-{
-    (void)desc;
-    (void)cache_path;
-    return pfb_internal_fail(PFB_E_UNSUPPORTED, "tuning is not built yet");
-}

@@ -1,0 +1,195 @@
+// Fused adjoint of the filter bank: inverse FFT, sample gradient and tap
+// gradient in one pass.
+//
+// For a real loss with frequency-spectra gradient gY (torch convention), the
+// adjoint of the DFT of Sec. 2, Eq. (2) gives gy = unnormalised inverse DFT
+// of gY, and the adjoint of the FIR of Algorithm 1 gives
+//   gx[p][c] = sum_{t < T} h[t][c] gy[p - t][c]      (gy = 0 outside [0, S))
+//   gh[t][c] = sum_p Re(conj(gy[p - t][c]) x[p][c])  (p = s + t)
+// Both read, for output row p, the same last T rows of gy, so one register
+// window of gy per channel serves both.
+//
+// One workgroup owns all C channels of a tile of gx rows [p0, p0 + S_B) of
+// one stream. It walks gy rows q from p0 - (TP-1) upwards in chunks of RB:
+//   1. inverse FFT of RB rows of gY (HBM -> registers -> LDS row buffer);
+//   2. per channel: push each gy row into the window; for rows q >= p0 also
+//      load x[q], write gx[q] and accumulate the tap-gradient partials.
+// The first TP-1 rows of a tile only fill the window (they are recomputed
+// from gY by the previous tile). At the end each workgroup writes its
+// partial tap gradient, which a second small kernel sums in a fixed order.
+#include "fft_device.h"
+#include "launch.h"
+
+namespace pfb {
+
+template <int LOG2C, int TP, int CPT> struct BwdShape {
+    static constexpr int C = 1 << LOG2C;
+    static constexpr int NT = C / CPT;
+    using FL = FftLanes<LOG2C>;
+    static constexpr int G = FL::G;
+    static constexpr int NG = NT / G;
+    static constexpr int RB = 16 > TP ? 16 : TP;
+    static constexpr int ROUNDS = RB / NG;
+    // x rows prefetched; shallower for the largest register footprint
+    static constexpr int D = (TP >= 16 && CPT == 2) ? 4 : 8;
+    using S = FftShape<LOG2C, G>;
+    static_assert(G <= 64, "one transform per wave or less");
+    static_assert(NG >= 1 && RB % TP == 0 && RB % D == 0 && RB % NG == 0, "chunk shape");
+};
+
+constexpr int bwd_cpt(int log2c) { return log2c >= 10 ? 2 : 1; }
+
+template <int TP, int LOG2C, int CPT>
+__global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_bwd_kernel(BwdArgs a)
+{
+    using F = BwdShape<LOG2C, TP, CPT>;
+    using S = typename F::S;
+    constexpr int C = F::C;
+    constexpr int RB = F::RB;
+    constexpr int D = F::D;
+    constexpr int G = F::G;
+    __shared__ float2 lds[RB * S::PADDED];
+
+    const int tile = (int)(blockIdx.x % a.n_tiles);
+    const int b = (int)(blockIdx.x / a.n_tiles);
+    const int t = (int)threadIdx.x;
+    const int c0 = t * CPT;
+    const int64_t rows = a.S + a.T - 1; // gx rows
+    const int64_t p0 = (int64_t)tile * a.SB;
+    const int np = (int)((rows - p0) < a.SB ? (rows - p0) : a.SB);
+    const int64_t q0 = p0 - (TP - 1);  // first gy row walked
+    const int nq = np + TP - 1;        // gy rows walked
+    const int off = TP - a.T;
+    const bool want_gx = a.gx != nullptr;
+    const bool want_gh = a.part != nullptr;
+
+    // window slot j of output p holds gy[p - (TP-1) + j], tap t = TP-1-j
+    float hp[TP][CPT];
+    sfor<TP>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        sfor<CPT>([&](auto k) { hp[j][k] = (j >= off) ? a.h[(int64_t)(TP - 1 - j) * C + c0 + k] : 0.0f; });
+    });
+    float acc[TP][CPT];
+    sfor<TP>([&](auto j) { sfor<CPT>([&](auto k) { acc[j][k] = 0.0f; }); });
+
+    const float2 *xb = a.x + (int64_t)b * rows * C;
+    const float2 *gYb = a.gY + (int64_t)b * a.S * C;
+    float2 *gxb = want_gx ? a.gx + (int64_t)b * rows * C : nullptr;
+    auto ldx = [&](int64_t row, float2 (&o)[CPT]) {
+        if (want_gh && row < rows)
+            Loader<DT_C64, CPT>::load(xb, row * C + c0, o);
+        else
+            sfor<CPT>([&](auto k) { o[k] = make_float2(0.0f, 0.0f); });
+    };
+
+    float2 w[TP][CPT];
+    float2 pf[D][CPT]; // x rows p0 + k, prefetched
+    sfor<D>([&](auto k) {
+        if (k < np)
+            ldx(p0 + k, pf[k]);
+    });
+
+    const int gid = t / G;
+    const int lane = t % G;
+    for (int base = 0; base < nq; base += RB) {
+        // 1. inverse FFT of gY rows q0+base .. q0+base+RB-1 into LDS
+#pragma unroll 1
+        for (int round = 0; round < F::ROUNDS; ++round) {
+            const int r = round * F::NG + gid;
+            const int64_t q = q0 + base + r;
+            float2 *row = lds + r * S::PADDED;
+            if (q >= 0 && q < a.S && base + r < nq) {
+                const float2 *src = gYb + q * C;
+                fft_run<LOG2C, G, true, false>(
+                    lane, row, a.tw, [&](int idx) { return src[idx]; },
+                    [&](int idx, float2 v) { row[S::pad(idx)] = v; });
+            } else {
+                for (int i = lane; i < C; i += G)
+                    row[S::pad(i)] = make_float2(0.0f, 0.0f);
+            }
+        }
+        __syncthreads();
+        // 2. sample gradient and tap-gradient partials
+        sfor<RB>([&](auto jjc) {
+            constexpr int jj = decltype(jjc)::value;
+            const int i = base + jj; // gy row q0 + i
+            if (i < nq) {
+                sfor<CPT>([&](auto k) { w[jj % TP][k] = lds[jj * S::PADDED + S::pad(c0 + k)]; });
+                const int o = i - (TP - 1); // output row p0 + o
+                if (o >= 0) {
+                    // x[p0 + o] arrives from the prefetch ring
+                    // ring slot of x[p0 + o]: o mod D, a constant because base
+                    // is a multiple of RB (itself a multiple of D)
+                    constexpr int slot = ((jj - (TP - 1)) % D + D) % D;
+                    float2 xv[CPT];
+                    sfor<CPT>([&](auto k) { xv[k] = pf[slot][k]; });
+                    if (o + D < np)
+                        ldx(p0 + o + D, pf[slot]);
+                    float2 g[CPT];
+                    sfor<CPT>([&](auto k) {
+                        float gr = 0.0f, gi = 0.0f;
+                        sfor<TP>([&](auto jc) {
+                            constexpr int j = decltype(jc)::value;
+                            // slot of gy[p - (TP-1) + j]: (jj - (TP-1) + j) mod TP
+                            const float2 v = w[(jj + 1 + j) % TP][k];
+                            gr = __builtin_fmaf(hp[j][k], v.x, gr);
+                            gi = __builtin_fmaf(hp[j][k], v.y, gi);
+                            acc[j][k] = __builtin_fmaf(v.x, xv[k].x, __builtin_fmaf(v.y, xv[k].y, acc[j][k]));
+                        });
+                        g[k] = make_float2(gr, gi);
+                    });
+                    if (want_gx && o < np)
+                        store_c64_nt<CPT>(gxb + (p0 + o) * C + c0, g);
+                }
+            }
+        });
+        __syncthreads();
+    }
+    if (want_gh) {
+        float *pb = a.part + ((int64_t)b * a.n_tiles + tile) * (int64_t)a.T * C + c0;
+        sfor<TP>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            const int tt = TP - 1 - j;
+            if (tt < a.T)
+                sfor<CPT>([&](auto k) { pb[(int64_t)tt * C + k] = acc[j][k]; });
+        });
+    }
+}
+
+bool fused_bwd_supported(int tp, int log2c)
+{
+    return log2c >= 8 && log2c <= 10 && (tp == 4 || tp == 8 || tp == 16);
+}
+
+template <int TP, int LOG2C> static hipError_t launch_bwd_t(const BwdArgs &a, hipStream_t st)
+{
+    const int64_t blocks = (int64_t)a.B * a.n_tiles;
+    if (blocks <= 0)
+        return hipSuccess;
+    constexpr int CPT = bwd_cpt(LOG2C);
+    hipLaunchKernelGGL((fused_bwd_kernel<TP, LOG2C, CPT>), dim3((unsigned)blocks), dim3((1 << LOG2C) / CPT), 0, st,
+                       a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fused_bwd(const BwdArgs &a, int tp, int log2c, hipStream_t st)
+{
+#define PFB_BWD_C(L2)                                                                                        \
+    case L2:                                                                                                 \
+        switch (tp) {                                                                                        \
+        case 4: return launch_bwd_t<4, L2>(a, st);                                                           \
+        case 8: return launch_bwd_t<8, L2>(a, st);                                                           \
+        case 16: return launch_bwd_t<16, L2>(a, st);                                                         \
+        default: return hipErrorInvalidValue;                                                                \
+        }
+    switch (log2c) {
+        PFB_BWD_C(8)
+        PFB_BWD_C(9)
+        PFB_BWD_C(10)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef PFB_BWD_C
+}
+
+} // namespace pfb

@@ -9,7 +9,22 @@
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 
+#include <utility>
+
 namespace pfb {
+
+template <int N, class F, int... Is>
+__device__ __forceinline__ void sfor_impl(F &&f, std::integer_sequence<int, Is...>)
+{
+    (f(std::integral_constant<int, Is>{}), ...);
+}
+// Compile-time loop: calls f(std::integral_constant<int, i>) for i = 0..N-1,
+// so register-array indices derived from i are constants (fully unrolled
+// regardless of the unroller's size limits).
+template <int N, class F> __device__ __forceinline__ void sfor(F &&f)
+{
+    sfor_impl<N>(f, std::make_integer_sequence<int, N>{});
+}
 
 enum Dtype { DT_C64 = 0, DT_CI16 = 1, DT_CI8 = 2, DT_CF16 = 3 };
 
@@ -137,6 +152,32 @@ template <int V> struct Loader<DT_CF16, V> {
     }
 };
 
+typedef float v2f_t __attribute__((ext_vector_type(2)));
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+
+// Streaming store of one complex float32 value: output that is written once
+// and not read back by this pass is marked non-temporal.
+__device__ __forceinline__ void store_nt(float2 *p, float2 v)
+{
+    v2f_t w = {v.x, v.y};
+    __builtin_nontemporal_store(w, reinterpret_cast<v2f_t *>(p));
+}
+
+// Streaming store of V consecutive complex float32 values (V in {1, 2, 4}).
+template <int V>
+__device__ __forceinline__ void store_c64_nt(float2 *p, const float2 (&v)[V])
+{
+    if constexpr (V == 1) {
+        store_nt(p, v[0]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < V; k += 2) {
+            v4f_t w = {v[k].x, v[k].y, v[k + 1].x, v[k + 1].y};
+            __builtin_nontemporal_store(w, reinterpret_cast<v4f_t *>(p + k));
+        }
+    }
+}
+
 // Store V consecutive complex float32 values.
 template <int V>
 __device__ __forceinline__ void store_c64(float2 *p, const float2 (&v)[V])
@@ -154,16 +195,5 @@ __device__ __forceinline__ void store_c64(float2 *p, const float2 (&v)[V])
 // Lane and wave indices for 1-D blocks.
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
 __device__ __forceinline__ int wave_id() { return (int)(threadIdx.x >> 6); }
-
-// Spread consecutive block indices over the 8 XCDs so that each XCD receives
-// a contiguous range of logical blocks (blocks are dispatched round robin
-// over XCDs). Neighbouring tiles then share an L2.
-__device__ __forceinline__ int64_t xcd_logical_block(int64_t bid, int64_t nblocks)
-{
-    constexpr int64_t NXCD = 8;
-    if (nblocks < NXCD || (nblocks % NXCD) != 0)
-        return bid;
-    return (bid % NXCD) * (nblocks / NXCD) + bid / NXCD;
-}
 
 } // namespace pfb

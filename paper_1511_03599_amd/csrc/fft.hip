@@ -35,7 +35,7 @@ __global__ __launch_bounds__(FftKernelShape<LOG2C>::NT) void fft_kernel(FftArgs 
     float2 *out = a.out + g * a.out_gstride + r * C;
     fft_run<LOG2C, G, INV, false>(
         lane, lds + gid * S::PADDED, a.tw, [&](int idx) { return in[idx]; },
-        [&](int idx, float2 v) { out[idx] = v; });
+        [&](int idx, float2 v) { store_nt(out + idx, v); });
 }
 
 template <int LOG2C> static hipError_t launch_fft_t(const FftArgs &a, bool inv, hipStream_t st)

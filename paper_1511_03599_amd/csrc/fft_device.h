@@ -22,23 +22,10 @@
 // contiguous and load as R/2 aligned 16-byte vectors.
 #pragma once
 
-#include <utility>
-
 #include "device_common.h"
 #include "fft_schedule.h"
 
 namespace pfb {
-
-template <int N, class F, int... Is>
-__device__ __forceinline__ void sfor_impl(F &&f, std::integer_sequence<int, Is...>)
-{
-    (f(std::integral_constant<int, Is>{}), ...);
-}
-// Compile-time loop: calls f(std::integral_constant<int, i>) for i = 0..N-1.
-template <int N, class F> __device__ __forceinline__ void sfor(F &&f)
-{
-    sfor_impl<N>(f, std::make_integer_sequence<int, N>{});
-}
 
 // cos(2 pi e / 16) and sin(2 pi e / 16).
 constexpr float cos16(int e)

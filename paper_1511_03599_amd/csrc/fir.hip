@@ -24,14 +24,18 @@
 
 namespace pfb {
 
+// Prefetch depth (rows in flight per lane) for each padded tap count: deep
+// where the window is small, shallower where registers are scarce.
+constexpr int fir_prefetch(int tp) { return tp <= 16 ? 16 : 8; }
+
 template <int DT, int TP, int CPT, int D, bool REV>
 __global__ __launch_bounds__(256) void fir_kernel(FirArgs a)
 {
     constexpr int U = TP > D ? TP : D; // outputs per unrolled step
     static_assert(U % TP == 0 && U % D == 0, "unroll");
-    const int64_t nblocks = gridDim.x;
-    const int64_t lb = xcd_logical_block(blockIdx.x, nblocks);
-    const int64_t gw = lb * (blockDim.x >> 6) + wave_id();
+    // Consecutive waves take consecutive channel chunks, then consecutive
+    // tiles, so the waves resident at any time sweep one narrow band of rows.
+    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave_id();
     const int64_t total = (int64_t)a.B * a.n_tiles * a.n_cchunks;
     if (gw >= total)
         return;
@@ -49,61 +53,54 @@ __global__ __launch_bounds__(256) void fir_kernel(FirArgs a)
     const int off = TP - a.T;
 
     float hp[CPT][TP];
-#pragma unroll
-    for (int j = 0; j < TP; ++j) {
+    sfor<TP>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
         const int t = j - off;
-#pragma unroll
-        for (int k = 0; k < CPT; ++k)
+        sfor<CPT>([&](auto k) {
             hp[k][j] = (t >= 0 && active) ? a.h[(int64_t)(REV ? a.T - 1 - t : t) * a.C + c0 + k] : 0.0f;
-    }
+        });
+    });
 
     const char *xb = reinterpret_cast<const char *>(a.x) + (int64_t)b * a.in_bstride * SampleBytes<DT>::value;
     auto ld = [&](int64_t row, float2 (&o)[CPT]) {
         if (active && row >= 0 && row < a.in_rows) {
             Loader<DT, CPT>::load(xb, row * a.C + c0, o);
         } else {
-#pragma unroll
-            for (int k = 0; k < CPT; ++k)
-                o[k] = make_float2(0.0f, 0.0f);
+            sfor<CPT>([&](auto k) { o[k] = make_float2(0.0f, 0.0f); });
         }
     };
 
     float2 w[TP][CPT];
     float2 pf[D][CPT];
-#pragma unroll
-    for (int j = 0; j < TP - 1; ++j)
-        ld(row0 + j, w[j]);
-#pragma unroll
-    for (int k = 0; k < D; ++k)
+    sfor<TP - 1>([&](auto j) { ld(row0 + j, w[j]); });
+    sfor<D>([&](auto k) {
         if (k < nout)
             ld(row0 + TP - 1 + k, pf[k]);
+    });
 
     float2 *yb = a.y + (int64_t)b * a.y_bstride + (s_begin - a.out_first) * a.C + c0;
     for (int base = 0; base < nout; base += U) {
-#pragma unroll
-        for (int jj = 0; jj < U; ++jj) {
+        sfor<U>([&](auto jjc) {
+            constexpr int jj = decltype(jjc)::value;
             const int o = base + jj;
             if (o < nout) {
-#pragma unroll
-                for (int k = 0; k < CPT; ++k)
-                    w[(jj + TP - 1) % TP][k] = pf[jj % D][k];
+                sfor<CPT>([&](auto k) { w[(jj + TP - 1) % TP][k] = pf[jj % D][k]; });
                 if (o + D < nout)
                     ld(row0 + o + D + TP - 1, pf[jj % D]);
                 float2 acc[CPT];
-#pragma unroll
-                for (int k = 0; k < CPT; ++k) {
+                sfor<CPT>([&](auto k) {
                     float ar = 0.0f, ai = 0.0f;
-#pragma unroll
-                    for (int j = 0; j < TP; ++j) {
+                    sfor<TP>([&](auto jc) {
+                        constexpr int j = decltype(jc)::value;
                         ar = __builtin_fmaf(hp[k][j], w[(jj + j) % TP][k].x, ar);
                         ai = __builtin_fmaf(hp[k][j], w[(jj + j) % TP][k].y, ai);
-                    }
+                    });
                     acc[k] = make_float2(ar, ai);
-                }
+                });
                 if (active)
-                    store_c64<CPT>(yb + (int64_t)o * a.C, acc);
+                    store_c64_nt<CPT>(yb + (int64_t)o * a.C, acc);
             }
-        }
+        });
     }
 }
 
@@ -136,25 +133,20 @@ __global__ __launch_bounds__(256) void gh_partial_kernel(GhArgs a)
     auto ldg = [&](int64_t s) -> float2 { return active ? gb[s * a.C] : make_float2(0.0f, 0.0f); };
 
     float acc[TP];
-#pragma unroll
-    for (int j = 0; j < TP; ++j)
-        acc[j] = 0.0f;
+    sfor<TP>([&](auto j) { acc[j] = 0.0f; });
     float2 w[TP];
     float2 pf[D];
     float2 pg[D];
-#pragma unroll
-    for (int j = 0; j < TP - 1; ++j)
-        w[j] = ldx(s_begin + j);
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
+    sfor<TP - 1>([&](auto j) { w[j] = ldx(s_begin + j); });
+    sfor<D>([&](auto k) {
         if (k < nout) {
             pf[k] = ldx(s_begin + TP - 1 + k);
             pg[k] = ldg(s_begin + k);
         }
-    }
+    });
     for (int base = 0; base < nout; base += U) {
-#pragma unroll
-        for (int jj = 0; jj < U; ++jj) {
+        sfor<U>([&](auto jjc) {
+            constexpr int jj = decltype(jjc)::value;
             const int o = base + jj;
             if (o < nout) {
                 w[(jj + TP - 1) % TP] = pf[jj % D];
@@ -163,20 +155,20 @@ __global__ __launch_bounds__(256) void gh_partial_kernel(GhArgs a)
                     pf[jj % D] = ldx(s_begin + o + D + TP - 1);
                     pg[jj % D] = ldg(s_begin + o + D);
                 }
-#pragma unroll
-                for (int j = 0; j < TP; ++j) {
+                sfor<TP>([&](auto jc) {
+                    constexpr int j = decltype(jc)::value;
                     const float2 xv = w[(jj + j) % TP];
                     acc[j] = __builtin_fmaf(g.x, xv.x, __builtin_fmaf(g.y, xv.y, acc[j]));
-                }
+                });
             }
-        }
+        });
     }
     if (active) {
         float *pb = a.part + ((int64_t)b * a.n_tiles + tile) * (int64_t)a.T * a.C + c;
-#pragma unroll
-        for (int j = 0; j < TP; ++j)
+        sfor<TP>([&](auto j) {
             if (j < a.T)
                 pb[(int64_t)j * a.C] = acc[j];
+        });
     }
 }
 
@@ -208,7 +200,7 @@ __global__ __launch_bounds__(256) void gh_reduce_kernel(const float *__restrict_
 template <int DT, int TP, int CPT, bool REV>
 static hipError_t launch_fir_t(const FirArgs &a, hipStream_t st)
 {
-    constexpr int D = TP >= 64 ? 8 : 16;
+    constexpr int D = fir_prefetch(TP);
     const int64_t total = (int64_t)a.B * a.n_tiles * a.n_cchunks;
     const int64_t blocks = (total + 3) / 4;
     if (blocks <= 0)
@@ -223,12 +215,16 @@ static hipError_t launch_fir_dt(const FirArgs &a, int tp, int cpt, hipStream_t s
 #define PFB_FIR_CASE(TPV)                                                                                    \
     case TPV:                                                                                                \
         return cpt == 2 ? launch_fir_t<DT, TPV, 2, REV>(a, st) : launch_fir_t<DT, TPV, 1, REV>(a, st);
+    // two channels per lane only where the doubled window still fits in
+    // registers; the larger windows run one channel per lane
     switch (tp) {
         PFB_FIR_CASE(4)
         PFB_FIR_CASE(8)
         PFB_FIR_CASE(16)
-        PFB_FIR_CASE(32)
-        PFB_FIR_CASE(64)
+    case 32:
+        return launch_fir_t<DT, 32, 1, REV>(a, st);
+    case 64:
+        return launch_fir_t<DT, 64, 1, REV>(a, st);
     default:
         return hipErrorInvalidValue;
     }
@@ -255,7 +251,7 @@ hipError_t launch_fir(const FirArgs &a, int dtype, int tp, int cpt, bool rev, hi
 
 template <int TP> static hipError_t launch_gh_t(const GhArgs &a, hipStream_t st)
 {
-    constexpr int D = TP >= 64 ? 8 : 16;
+    constexpr int D = fir_prefetch(TP);
     const int64_t total = (int64_t)a.B * a.n_tiles * a.n_cchunks;
     const int64_t blocks = (total + 3) / 4;
     if (blocks <= 0)
@@ -277,10 +273,13 @@ hipError_t launch_gh(const GhArgs &a, int tp, float *gh, hipStream_t st)
     }
     if (e != hipSuccess)
         return e;
-    const int64_t tc = (int64_t)a.T * a.C;
-    const int64_t n_parts = (int64_t)a.B * a.n_tiles;
-    hipLaunchKernelGGL(gh_reduce_kernel, dim3((unsigned)((tc + 255) / 256)), dim3(256), 0, st, a.part, gh,
-                       n_parts, tc);
+    return launch_gh_reduce(a.part, gh, (int64_t)a.B * a.n_tiles, (int64_t)a.T * a.C, st);
+}
+
+hipError_t launch_gh_reduce(const float *part, float *gh, int64_t n_parts, int64_t tc, hipStream_t st)
+{
+    hipLaunchKernelGGL(gh_reduce_kernel, dim3((unsigned)((tc + 255) / 256)), dim3(256), 0, st, part, gh, n_parts,
+                       tc);
     return hipGetLastError();
 }
 

@@ -49,7 +49,7 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_fwd_kernel(FusedArgs
     constexpr int G = F::G;
     __shared__ float2 lds[RB * S::PADDED];
 
-    const int64_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int64_t lb = blockIdx.x;
     const int tile = (int)(lb % a.n_tiles);
     const int b = (int)(lb / a.n_tiles);
     const int t = (int)threadIdx.x;
@@ -127,7 +127,7 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_fwd_kernel(FusedArgs
                 lane, row, a.tw, [&](int idx) { return row[S::pad(idx)]; },
                 [&](int idx, float2 v) {
                     if (valid)
-                        out[idx] = v;
+                        store_nt(out + idx, v);
                 });
         }
         __syncthreads();

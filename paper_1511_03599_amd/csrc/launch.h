@@ -59,11 +59,27 @@ struct FusedArgs {
     int64_t S;
 };
 
+// Fused adjoint: one workgroup per tile of S_B gx rows of one stream.
+struct BwdArgs {
+    const float2 *x;     // [B][S+T-1][C]
+    const float *h;      // [T][C]
+    const float2 *gY;    // [B][S][C]
+    float2 *gx;          // [B][S+T-1][C] or NULL
+    float *part;         // [B*n_tiles][T][C] tap-gradient partials, or NULL
+    const float2 *tw;
+    int T, B;
+    int SB, n_tiles;     // gx rows per tile, tiles per stream
+    int64_t S;
+};
+
 hipError_t launch_fir(const FirArgs &a, int dtype, int tp, int cpt, bool rev, hipStream_t st);
 hipError_t launch_gh(const GhArgs &a, int tp, float *gh, hipStream_t st);
 hipError_t launch_fft(const FftArgs &a, int log2c, bool inv, hipStream_t st);
 hipError_t launch_fused(const FusedArgs &a, int dtype, int tp, int log2c, hipStream_t st);
 bool fused_supported(int dtype, int tp, int log2c);
+hipError_t launch_fused_bwd(const BwdArgs &a, int tp, int log2c, hipStream_t st);
+bool fused_bwd_supported(int tp, int log2c);
+hipError_t launch_gh_reduce(const float *part, float *gh, int64_t n_parts, int64_t tc, hipStream_t st);
 int fused_rows_per_chunk(int tp, int log2c);
 
 } // namespace pfb

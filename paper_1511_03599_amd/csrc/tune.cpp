@@ -7,8 +7,11 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <string>
+#include <vector>
 
+#include "launch.h"
 #include "tune.h"
 
 namespace pfb {
@@ -39,8 +42,16 @@ static bool parse_kv(const char *tok, const char *key, int *val)
     return true;
 }
 
+static thread_local const TuneEntry *g_override = nullptr;
+
+void tune_set_override(const TuneEntry *e) { g_override = e; }
+
 bool tune_lookup(const pfb_desc &d, TuneEntry *out)
 {
+    if (g_override) {
+        *out = *g_override;
+        return true;
+    }
     const char *path = std::getenv("PFB_TUNE_CACHE");
     if (!path || !*path)
         return false;
@@ -68,6 +79,7 @@ bool tune_lookup(const pfb_desc &d, TuneEntry *out)
             parse_kv(tok, "fir_sb", &e.fir_sb);
             parse_kv(tok, "fused_sb", &e.fused_sb);
             parse_kv(tok, "chunk_mib", &e.chunk_mib);
+            parse_kv(tok, "bwd_sb", &e.bwd_sb);
         }
         best = e; // the last matching line wins
         found = true;
@@ -79,3 +91,176 @@ bool tune_lookup(const pfb_desc &d, TuneEntry *out)
 }
 
 } // namespace pfb
+
+// ----------------------------------------------------------------------------
+// The tuner
+// ----------------------------------------------------------------------------
+
+namespace {
+
+struct Buffers {
+    void *x = nullptr, *taps = nullptr, *y = nullptr;
+    ~Buffers()
+    {
+        if (x)
+            (void)hipFree(x);
+        if (taps)
+            (void)hipFree(taps);
+        if (y)
+            (void)hipFree(y);
+    }
+};
+
+int bytes_per_sample(int dt) { return dt == PFB_C64 ? 8 : dt == PFB_CI8 ? 2 : 4; }
+
+int padded_taps(int T)
+{
+    int tp = 4;
+    while (tp < T)
+        tp *= 2;
+    return tp;
+}
+
+int ilog2_exact(int64_t v)
+{
+    if (v <= 0 || (v & (v - 1)))
+        return -1;
+    int l = 0;
+    while ((int64_t(1) << l) < v)
+        ++l;
+    return l;
+}
+
+} // namespace
+
+using namespace pfb;
+
+// Time one forward call of a plan built with configuration `e` (median of
+// `reps` event-timed calls after two warm-up calls). Returns < 0 on failure.
+static double time_candidate(const pfb_desc &d, const TuneEntry &e, Buffers &buf, hipStream_t st, int reps)
+{
+    tune_set_override(&e);
+    pfb_plan *p = nullptr;
+    pfb_status s = pfb_plan_create(&d, &p);
+    tune_set_override(nullptr);
+    if (s != PFB_OK)
+        return -1.0;
+    const bool fir_only = d.flags & PFB_FIR_ONLY;
+    void *y = fir_only ? buf.y : nullptr;
+    void *Y = fir_only ? nullptr : buf.y;
+    double best = -1.0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+        bool ok = true;
+        for (int i = 0; i < 2 && ok; ++i)
+            ok = pfb_execute(p, buf.x, (const float *)buf.taps, y, Y, st) == PFB_OK;
+        std::vector<float> ts;
+        for (int i = 0; i < reps && ok; ++i) {
+            ok = hipEventRecord(e0, st) == hipSuccess &&
+                 pfb_execute(p, buf.x, (const float *)buf.taps, y, Y, st) == PFB_OK &&
+                 hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+            float ms = 0.0f;
+            if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+                ts.push_back(ms);
+        }
+        if (ok && !ts.empty()) {
+            std::sort(ts.begin(), ts.end());
+            best = ts[ts.size() / 2];
+        }
+    }
+    if (e0)
+        (void)hipEventDestroy(e0);
+    if (e1)
+        (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(st);
+    pfb_plan_destroy(p);
+    return best;
+}
+
+extern "C" pfb_status pfb_tune(const pfb_desc *desc, const char *cache_path)
+{
+    pfb_status st = pfb_internal_validate(desc, false);
+    if (st != PFB_OK)
+        return st;
+    if (!cache_path || !*cache_path)
+        return pfb_internal_fail(PFB_E_INVALID, "cache_path is empty");
+    const pfb_desc d = *desc;
+    const int64_t rows = d.spectra + d.taps - 1;
+    Buffers buf;
+    const size_t xbytes = (size_t)(d.batch * rows * d.channels) * bytes_per_sample(d.dtype);
+    const size_t ybytes = (size_t)(d.batch * d.spectra * d.channels) * 8;
+    if (hipMalloc(&buf.x, xbytes) != hipSuccess || hipMalloc(&buf.taps, (size_t)d.taps * d.channels * 4) != hipSuccess ||
+        hipMalloc(&buf.y, ybytes) != hipSuccess)
+        return pfb_internal_fail(PFB_E_NOMEM, "tuner buffers");
+    // a small non-zero pattern (timing does not depend on the values)
+    if (hipMemset(buf.x, 0x11, xbytes) != hipSuccess || hipMemset(buf.taps, 0x11, (size_t)d.taps * d.channels * 4) != hipSuccess)
+        return pfb_internal_fail(PFB_E_HIP, "tuner buffer fill");
+    hipStream_t s = nullptr;
+    const bool verbose = std::getenv("PFB_TUNE_VERBOSE") != nullptr;
+
+    std::vector<TuneEntry> cands;
+    const int tp = padded_taps(d.taps);
+    const bool fir_only = d.flags & PFB_FIR_ONLY;
+    const bool cpt2 = tp <= 16 && d.channels % 2 == 0;
+    auto add_split = [&](int path) {
+        for (int cpt : {1, 2}) {
+            if (cpt == 2 && !cpt2)
+                continue;
+            for (int sb : {16, 32, 64, 128}) {
+                if (path == 2) {
+                    TuneEntry e;
+                    e.fir_cpt = cpt;
+                    e.fir_sb = sb;
+                    cands.push_back(e);
+                } else {
+                    for (int mib : {32, 64, 128, 256}) {
+                        TuneEntry e;
+                        e.path = 1;
+                        e.fir_cpt = cpt;
+                        e.fir_sb = sb;
+                        e.chunk_mib = mib;
+                        cands.push_back(e);
+                    }
+                }
+            }
+        }
+    };
+    if (fir_only) {
+        add_split(2);
+    } else {
+        const int l2 = ilog2_exact(d.channels);
+        if (!(d.flags & (PFB_NO_FUSE | PFB_PLAIN)) && fused_supported(d.dtype, tp, l2)) {
+            const int rb = tp > 16 ? tp : 16;
+            for (int m : {1, 2, 4, 8, 16, 32}) {
+                TuneEntry e;
+                e.path = 0;
+                e.fused_sb = rb * m;
+                cands.push_back(e);
+            }
+        }
+        add_split(1);
+    }
+    const int reps = 7;
+    double best_t = -1.0;
+    TuneEntry best;
+    for (const TuneEntry &e : cands) {
+        const double t = time_candidate(d, e, buf, s, reps);
+        if (verbose)
+            std::fprintf(stderr, "pfb_tune: path=%d fir_cpt=%d fir_sb=%d fused_sb=%d chunk_mib=%d -> %.4f ms\n",
+                         e.path, e.fir_cpt, e.fir_sb, e.fused_sb, e.chunk_mib, t);
+        if (t > 0 && (best_t < 0 || t < best_t)) {
+            best_t = t;
+            best = e;
+        }
+    }
+    if (best_t < 0)
+        return pfb_internal_fail(PFB_E_HIP, "no tuning candidate ran");
+    FILE *f = std::fopen(cache_path, "a");
+    if (!f)
+        return pfb_internal_fail(PFB_E_INVALID, "cannot open the tuning cache for writing");
+    std::fprintf(f, "%s %d %d %d %d %lld path=%d fir_cpt=%d fir_sb=%d fused_sb=%d chunk_mib=%d ms=%.5f\n",
+                 device_arch_name().c_str(), d.dtype, d.channels, d.taps, d.batch, (long long)d.spectra, best.path,
+                 best.fir_cpt, best.fir_sb, best.fused_sb, best.chunk_mib, best_t);
+    std::fclose(f);
+    return PFB_OK;
+}

@@ -2,6 +2,8 @@
 // cache and the batched-plan module.
 #pragma once
 
+#include <string>
+
 #include "../../include/pfb.h"
 
 namespace pfb {
@@ -13,12 +15,19 @@ struct TuneEntry {
     int fir_sb = 0;      // FIR rows per tile
     int fused_sb = 0;    // fused rows per tile
     int chunk_mib = 0;   // split-path chunk size
+    int bwd_sb = 0;      // fused adjoint rows per tile
 };
 
 // Look the descriptor up in the cache file named by PFB_TUNE_CACHE. Returns
 // false (and leaves *out untouched) when the variable is unset, the file is
 // missing or unreadable, or has no entry for this descriptor.
 bool tune_lookup(const pfb_desc &d, TuneEntry *out);
+
+// While non-NULL on the calling thread, plans take this configuration instead
+// of the cache (used by the tuner to time candidates).
+void tune_set_override(const TuneEntry *e);
+
+std::string device_arch_name();
 
 } // namespace pfb
 

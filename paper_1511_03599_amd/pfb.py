@@ -44,7 +44,8 @@ class Desc(ctypes.Structure):
 class PlanInfo(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("fir_rows", ctypes.c_int32), ("fir_cpt", ctypes.c_int32),
                 ("padded_taps", ctypes.c_int32), ("workspace_bytes", ctypes.c_int64),
-                ("chunk_rows", ctypes.c_int64)]
+                ("chunk_rows", ctypes.c_int64), ("backward_fused", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 EXPORTED = ("pfb_plan_create", "pfb_execute", "pfb_backward", "pfb_plan_create_batched",
@@ -132,7 +133,7 @@ class Plan:
         check(lib().pfb_plan_get_info(self._h, ctypes.byref(i)))
         return {"path": PATH_NAMES.get(i.path, i.path), "fir_rows": i.fir_rows, "fir_cpt": i.fir_cpt,
                 "padded_taps": i.padded_taps, "workspace_bytes": i.workspace_bytes,
-                "chunk_rows": i.chunk_rows}
+                "chunk_rows": i.chunk_rows, "backward_fused": bool(i.backward_fused)}
 
     def _check_x(self, x):
         want = (self.B, self.rows, self.C)
@@ -178,6 +179,12 @@ class Plan:
         check(lib().pfb_backward(self._h, _ptr(x), _ptr(h), _ptr(gY), _ptr(gx if want_gx else None),
                                  _ptr(gh if want_gh else None), _stream(stream)))
         return (gx if want_gx else None), (gh if want_gh else None)
+
+    def tune(self, cache_path: str):
+        """Run the library's tuner for this plan's descriptor (writes one line
+        to `cache_path`; plans created later read it via PFB_TUNE_CACHE)."""
+        d = make_desc(self.C, self.T, self.S, self.B, self.dtype, self.flags)
+        check(lib().pfb_tune(ctypes.byref(d), cache_path.encode()))
 
     def close(self):
         if getattr(self, "_h", None):

@@ -18,15 +18,19 @@ def pfbmod():
 
 
 @pytest.mark.parametrize("C,T,S,B", [(32, 4, 20, 2), (256, 8, 100, 2), (1024, 16, 80, 3), (4096, 5, 10, 1),
-                                     (64, 64, 100, 1), (1024, 33, 70, 1), (512, 1, 40, 2), (128, 16, 600, 1)])
-def test_backward_parity(dev, C, T, S, B):
+                                     (64, 64, 100, 1), (1024, 33, 70, 1), (512, 1, 40, 2), (128, 16, 600, 1),
+                                     (1024, 16, 700, 2), (256, 3, 530, 1), (512, 13, 257, 2)])
+@pytest.mark.parametrize("mode", ["default", "split"])
+def test_backward_parity(dev, C, T, S, B, mode):
     import torch
     pfb = pfbmod()
-    say(f"backward C={C} T={T} S={S} B={B}")
+    say(f"backward C={C} T={T} S={S} B={B} {mode}")
     x = synth.quantise(synth.complex_gaussian((B, S + T - 1, C), 700 + C), "c64")
     h = synth.random_taps(C, T, 701)
     gY = synth.quantise(synth.complex_gaussian((B, S, C), 702), "c64")
-    plan = pfb.Plan(C, T, S, B, "c64")
+    plan = pfb.Plan(C, T, S, B, "c64", pfb.NO_FUSE if mode == "split" else 0)
+    if mode == "split":
+        assert not plan.info()["backward_fused"]
     gx, gh = plan.backward(to_device(x, dev), taps_to_device(h, dev), to_device(gY, dev))
     torch.cuda.synchronize()
     gx_r, gh_r = oracle.pfb_adjoint(x, h, gY)
