@@ -107,6 +107,7 @@ struct pfb_plan {
     int gh_sb = 256;
     bool bwd_fused = false;      // fused adjoint kernel
     int bwd_sb = 256;            // gx rows per fused adjoint tile
+    int num_cus = 256;           // compute units of the plan's device
     // batched
     struct Batched *batched = nullptr;
 };
@@ -212,6 +213,32 @@ static pfb_status dev_alloc(void **p, int64_t bytes, const char *what)
 
 static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Rows per tile for a kernel that runs one workgroup per CU at a time: the
+// smallest multiple of `rb` that is at least `min_rows` and splits the
+// B*rows work into a whole number of rounds over the CUs (so that no CU
+// runs one tile more than the others at the end).
+static int balanced_tile_rows(int64_t B, int64_t rows, int rb, int64_t min_rows, int cus)
+{
+    const int64_t max_tiles = B * ceil_div(rows, ceil_div(min_rows, rb) * rb);
+    int64_t best_sb = ceil_div(min_rows, rb) * rb;
+    double best_eff = 0.0;
+    for (int64_t rounds = 1; rounds * cus <= max_tiles * 2 + cus; ++rounds) {
+        // tiles per stream needed for `rounds` full rounds
+        const int64_t tiles_total = rounds * cus;
+        const int64_t tiles_per_stream = ceil_div(tiles_total, B);
+        int64_t sb = ceil_div(ceil_div(rows, tiles_per_stream), rb) * rb;
+        if (sb < rb)
+            sb = rb;
+        const int64_t n = B * ceil_div(rows, sb);
+        const double eff = (double)n / (double)(ceil_div(n, cus) * cus);
+        if (sb >= min_rows && (eff > best_eff + 1e-9 || (eff >= best_eff - 1e-9 && sb > best_sb && eff > 0.97))) {
+            best_eff = eff;
+            best_sb = sb;
+        }
+    }
+    return (int)best_sb;
+}
+
 // Rows per fused tile: short tiles (four chunks) so that many workgroups
 // run in launch order and the resident ones sweep a narrow band of rows; the
 // halo rows they share with the previous tile are then still cached.
@@ -229,6 +256,11 @@ static pfb_status plan_single(const pfb_desc *d, pfb_plan *p)
     p->d = *d;
     (void)hipGetDevice(&p->device);
     p->tp = padded_taps(d->taps);
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, p->device) == hipSuccess && prop.multiProcessorCount > 0)
+            p->num_cus = prop.multiProcessorCount;
+    }
     const bool fir_only = d->flags & PFB_FIR_ONLY;
     p->log2c = fir_only ? -1 : ilog2_exact(d->channels);
 
@@ -293,6 +325,9 @@ static pfb_status plan_single(const pfb_desc *d, pfb_plan *p)
             return st;
         if (d->dtype == PFB_C64) {
             p->bwd_fused = !(d->flags & (PFB_NO_FUSE | PFB_PLAIN)) && fused_bwd_supported(p->tp, p->log2c);
+            // at least 128 gx rows per tile (the T-1 halo rows are transformed
+            // twice and every tile writes a tap-gradient partial)
+            p->bwd_sb = balanced_tile_rows(d->batch, d->spectra + d->taps - 1, 16, 128, p->num_cus);
             if (tuned && te.bwd_sb >= 16 && te.bwd_sb <= 65536)
                 p->bwd_sb = te.bwd_sb;
             int64_t parts;

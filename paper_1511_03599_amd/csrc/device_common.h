@@ -11,6 +11,11 @@
 
 #include <utility>
 
+// Marks a lambda's call operator always-inline: the compile-time loops below
+// must expand completely so that register arrays indexed by their counters
+// stay in registers, however large the enclosing kernel is.
+#define PFB_INLINE __attribute__((always_inline))
+
 namespace pfb {
 
 template <int N, class F, int... Is>

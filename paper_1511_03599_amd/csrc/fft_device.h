@@ -50,10 +50,6 @@ template <int N, int E> __device__ __forceinline__ float2 twc(float2 v)
         return make_float2(-v.x, -v.y);
     } else if constexpr (e == 12) {
         return mul_pi(v);
-    } else if constexpr (e == 2 || e == 6 || e == 10 || e == 14) {
-        // W = (c, -s) with |c| = |s| = sqrt(1/2)
-        constexpr float c = cos16(e), s = sin16(e);
-        return make_float2((v.x * c) + (v.y * s), (v.y * c) - (v.x * s));
     } else {
         constexpr float c = cos16(e), s = sin16(e);
         return make_float2(__builtin_fmaf(v.x, c, v.y * s), __builtin_fmaf(v.y, c, -(v.x * s)));
@@ -89,18 +85,18 @@ template <int N1, int N2> __device__ __forceinline__ void dft_ct(float2 *v)
 {
     constexpr int N = N1 * N2;
     float2 a[N2][N1];
-    sfor<N2>([&](auto n2) {
-        sfor<N1>([&](auto n1) { a[n2][n1] = v[N2 * n1 + n2]; });
+    sfor<N2>([&](auto n2) PFB_INLINE {
+        sfor<N1>([&](auto n1) PFB_INLINE { a[n2][n1] = v[N2 * n1 + n2]; });
         Dft<N1>::run(a[n2]);
-        sfor<N1>([&](auto k1) {
+        sfor<N1>([&](auto k1) PFB_INLINE {
             a[n2][k1] = twc<N, decltype(n2)::value * decltype(k1)::value>(a[n2][k1]);
         });
     });
-    sfor<N1>([&](auto k1) {
+    sfor<N1>([&](auto k1) PFB_INLINE {
         float2 b[N2];
-        sfor<N2>([&](auto n2) { b[n2] = a[n2][k1]; });
+        sfor<N2>([&](auto n2) PFB_INLINE { b[n2] = a[n2][k1]; });
         Dft<N2>::run(b);
-        sfor<N2>([&](auto k2) { v[k1 + N1 * k2] = b[k2]; });
+        sfor<N2>([&](auto k2) PFB_INLINE { v[k1 + N1 * k2] = b[k2]; });
     });
 }
 template <> struct Dft<8> {
@@ -151,8 +147,13 @@ __device__ __forceinline__ void fft_run(int lane, float2 *lds, const float2 *__r
     constexpr int C = S::C;
     constexpr int E = S::E;
     float2 v[E];
+    // Opaque copy of the twiddle pointer: keeps the compiler from hoisting
+    // the twiddle loads of every pass out of a caller's loop over rows, which
+    // would hold them all in registers at once.
+    const float2 *twp = tw;
+    asm volatile("" : "+v"(twp));
 
-    sfor<S::NPASS>([&](auto pp) {
+    sfor<S::NPASS>([&](auto pp) PFB_INLINE {
         constexpr int P = decltype(pp)::value;
         constexpr int R = S::radix(P);
         constexpr int L = S::stride(P);
@@ -160,9 +161,9 @@ __device__ __forceinline__ void fft_run(int lane, float2 *lds, const float2 *__r
         constexpr int CR = C / R;
 
         // gather
-        sfor<NB>([&](auto q) {
+        sfor<NB>([&](auto q) PFB_INLINE {
             const int j = lane + G * decltype(q)::value;
-            sfor<R>([&](auto i) {
+            sfor<R>([&](auto i) PFB_INLINE {
                 const int idx = j + decltype(i)::value * CR;
                 float2 t;
                 if constexpr (P == 0) {
@@ -179,13 +180,13 @@ __device__ __forceinline__ void fft_run(int lane, float2 *lds, const float2 *__r
             group_sync<G>(); // every lane has read before any lane overwrites
 
         // twiddle and butterfly
-        sfor<NB>([&](auto q) {
+        sfor<NB>([&](auto q) PFB_INLINE {
             constexpr int Q = decltype(q)::value;
             const int j = lane + G * Q;
             if constexpr (L > 1) {
                 const int k = j & (L - 1);
-                const float4 *wp = reinterpret_cast<const float4 *>(tw + S::pass_offset(P) + k * R);
-                sfor<R / 2>([&](auto hh) {
+                const float4 *wp = reinterpret_cast<const float4 *>(twp + S::pass_offset(P) + k * R);
+                sfor<R / 2>([&](auto hh) PFB_INLINE {
                     constexpr int H = decltype(hh)::value;
                     const float4 w2 = wp[H];
                     if constexpr (H > 0)
@@ -198,9 +199,9 @@ __device__ __forceinline__ void fft_run(int lane, float2 *lds, const float2 *__r
 
         // scatter
         if constexpr (P == S::NPASS - 1) {
-            sfor<NB>([&](auto q) {
+            sfor<NB>([&](auto q) PFB_INLINE {
                 const int j = lane + G * decltype(q)::value;
-                sfor<R>([&](auto i) {
+                sfor<R>([&](auto i) PFB_INLINE {
                     float2 t = v[decltype(q)::value * R + decltype(i)::value];
                     if constexpr (INV)
                         t = conj2(t);
@@ -208,11 +209,11 @@ __device__ __forceinline__ void fft_run(int lane, float2 *lds, const float2 *__r
                 });
             });
         } else {
-            sfor<NB>([&](auto q) {
+            sfor<NB>([&](auto q) PFB_INLINE {
                 const int j = lane + G * decltype(q)::value;
                 const int k = j & (L - 1);
                 const int o = (j - k) * R + k;
-                sfor<R>([&](auto i) {
+                sfor<R>([&](auto i) PFB_INLINE {
                     lds[S::pad(o + decltype(i)::value * L)] = v[decltype(q)::value * R + decltype(i)::value];
                 });
             });

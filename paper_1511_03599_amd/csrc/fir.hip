@@ -19,89 +19,21 @@
 // Rows outside [0, in_rows) read as zero. The same kernel computes the
 // adjoint in the samples (REV: taps reversed, shift = off + T - 1), which is
 // the "full" correlation of the filtered-spectra gradient with the taps.
-#include "device_common.h"
+#include "fir_device.h"
 #include "launch.h"
 
 namespace pfb {
 
-// Prefetch depth (rows in flight per lane) for each padded tap count: deep
-// where the window is small, shallower where registers are scarce.
-constexpr int fir_prefetch(int tp) { return tp <= 16 ? 16 : 8; }
-
 template <int DT, int TP, int CPT, int D, bool REV>
 __global__ __launch_bounds__(256) void fir_kernel(FirArgs a)
 {
-    constexpr int U = TP > D ? TP : D; // outputs per unrolled step
-    static_assert(U % TP == 0 && U % D == 0, "unroll");
     // Consecutive waves take consecutive channel chunks, then consecutive
     // tiles, so the waves resident at any time sweep one narrow band of rows.
     const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave_id();
     const int64_t total = (int64_t)a.B * a.n_tiles * a.n_cchunks;
     if (gw >= total)
         return;
-    const int cch = (int)(gw % a.n_cchunks);
-    const int64_t rest = gw / a.n_cchunks;
-    const int tile = (int)(rest % a.n_tiles);
-    const int b = (int)(rest / a.n_tiles);
-
-    const int c0 = (cch * 64 + lane_id()) * CPT;
-    const bool active = c0 < a.C;
-    const int64_t s_begin = a.out_first + (int64_t)tile * a.SB;
-    const int64_t s_end = a.out_first + a.out_count;
-    const int nout = (int)((s_end - s_begin) < a.SB ? (s_end - s_begin) : a.SB);
-    const int64_t row0 = s_begin - a.shift; // input row of window slot 0
-    const int off = TP - a.T;
-
-    float hp[CPT][TP];
-    sfor<TP>([&](auto jc) {
-        constexpr int j = decltype(jc)::value;
-        const int t = j - off;
-        sfor<CPT>([&](auto k) {
-            hp[k][j] = (t >= 0 && active) ? a.h[(int64_t)(REV ? a.T - 1 - t : t) * a.C + c0 + k] : 0.0f;
-        });
-    });
-
-    const char *xb = reinterpret_cast<const char *>(a.x) + (int64_t)b * a.in_bstride * SampleBytes<DT>::value;
-    auto ld = [&](int64_t row, float2 (&o)[CPT]) {
-        if (active && row >= 0 && row < a.in_rows) {
-            Loader<DT, CPT>::load(xb, row * a.C + c0, o);
-        } else {
-            sfor<CPT>([&](auto k) { o[k] = make_float2(0.0f, 0.0f); });
-        }
-    };
-
-    float2 w[TP][CPT];
-    float2 pf[D][CPT];
-    sfor<TP - 1>([&](auto j) { ld(row0 + j, w[j]); });
-    sfor<D>([&](auto k) {
-        if (k < nout)
-            ld(row0 + TP - 1 + k, pf[k]);
-    });
-
-    float2 *yb = a.y + (int64_t)b * a.y_bstride + (s_begin - a.out_first) * a.C + c0;
-    for (int base = 0; base < nout; base += U) {
-        sfor<U>([&](auto jjc) {
-            constexpr int jj = decltype(jjc)::value;
-            const int o = base + jj;
-            if (o < nout) {
-                sfor<CPT>([&](auto k) { w[(jj + TP - 1) % TP][k] = pf[jj % D][k]; });
-                if (o + D < nout)
-                    ld(row0 + o + D + TP - 1, pf[jj % D]);
-                float2 acc[CPT];
-                sfor<CPT>([&](auto k) {
-                    float ar = 0.0f, ai = 0.0f;
-                    sfor<TP>([&](auto jc) {
-                        constexpr int j = decltype(jc)::value;
-                        ar = __builtin_fmaf(hp[k][j], w[(jj + j) % TP][k].x, ar);
-                        ai = __builtin_fmaf(hp[k][j], w[(jj + j) % TP][k].y, ai);
-                    });
-                    acc[k] = make_float2(ar, ai);
-                });
-                if (active)
-                    store_c64_nt<CPT>(yb + (int64_t)o * a.C, acc);
-            }
-        });
-    }
+    fir_wave_task<DT, TP, CPT, D, REV>(a, gw);
 }
 
 // Tap gradient, first stage: per tile of filtered spectra and per channel,

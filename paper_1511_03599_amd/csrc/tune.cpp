@@ -99,15 +99,12 @@ bool tune_lookup(const pfb_desc &d, TuneEntry *out)
 namespace {
 
 struct Buffers {
-    void *x = nullptr, *taps = nullptr, *y = nullptr;
+    void *x = nullptr, *taps = nullptr, *y = nullptr, *gx = nullptr, *gh = nullptr;
     ~Buffers()
     {
-        if (x)
-            (void)hipFree(x);
-        if (taps)
-            (void)hipFree(taps);
-        if (y)
-            (void)hipFree(y);
+        for (void *p : {x, taps, y, gx, gh})
+            if (p)
+                (void)hipFree(p);
     }
 };
 
@@ -135,9 +132,11 @@ int ilog2_exact(int64_t v)
 
 using namespace pfb;
 
-// Time one forward call of a plan built with configuration `e` (median of
-// `reps` event-timed calls after two warm-up calls). Returns < 0 on failure.
-static double time_candidate(const pfb_desc &d, const TuneEntry &e, Buffers &buf, hipStream_t st, int reps)
+// Time one forward (or, with `backward`, adjoint) call of a plan built with
+// configuration `e` (median of `reps` event-timed calls after two warm-up
+// calls). Returns < 0 on failure.
+static double time_candidate(const pfb_desc &d, const TuneEntry &e, Buffers &buf, hipStream_t st, int reps,
+                             bool backward = false)
 {
     tune_set_override(&e);
     pfb_plan *p = nullptr;
@@ -148,16 +147,20 @@ static double time_candidate(const pfb_desc &d, const TuneEntry &e, Buffers &buf
     const bool fir_only = d.flags & PFB_FIR_ONLY;
     void *y = fir_only ? buf.y : nullptr;
     void *Y = fir_only ? nullptr : buf.y;
+    auto call = [&]() {
+        if (backward)
+            return pfb_backward(p, buf.x, (const float *)buf.taps, buf.y, buf.gx, (float *)buf.gh, st);
+        return pfb_execute(p, buf.x, (const float *)buf.taps, y, Y, st);
+    };
     double best = -1.0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
         bool ok = true;
         for (int i = 0; i < 2 && ok; ++i)
-            ok = pfb_execute(p, buf.x, (const float *)buf.taps, y, Y, st) == PFB_OK;
+            ok = call() == PFB_OK;
         std::vector<float> ts;
         for (int i = 0; i < reps && ok; ++i) {
-            ok = hipEventRecord(e0, st) == hipSuccess &&
-                 pfb_execute(p, buf.x, (const float *)buf.taps, y, Y, st) == PFB_OK &&
+            ok = hipEventRecord(e0, st) == hipSuccess && call() == PFB_OK &&
                  hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
             float ms = 0.0f;
             if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
@@ -255,12 +258,34 @@ extern "C" pfb_status pfb_tune(const pfb_desc *desc, const char *cache_path)
     }
     if (best_t < 0)
         return pfb_internal_fail(PFB_E_HIP, "no tuning candidate ran");
+    // the adjoint's tile height, timed with the forward configuration chosen
+    if (!fir_only && d.dtype == PFB_C64) {
+        const size_t gxbytes = (size_t)(d.batch * rows * d.channels) * 8;
+        if (hipMalloc(&buf.gx, gxbytes) == hipSuccess &&
+            hipMalloc(&buf.gh, (size_t)d.taps * d.channels * 4) == hipSuccess &&
+            hipMemset(buf.y, 0x11, ybytes) == hipSuccess) {
+            double best_b = -1.0;
+            int best_sb = 0;
+            for (int sb : {0, 128, 256, 512, 1024}) {
+                TuneEntry e = best;
+                e.bwd_sb = sb;
+                const double t = time_candidate(d, e, buf, s, reps, true);
+                if (verbose)
+                    std::fprintf(stderr, "pfb_tune: backward bwd_sb=%d -> %.4f ms\n", sb, t);
+                if (t > 0 && (best_b < 0 || t < best_b)) {
+                    best_b = t;
+                    best_sb = sb;
+                }
+            }
+            best.bwd_sb = best_sb;
+        }
+    }
     FILE *f = std::fopen(cache_path, "a");
     if (!f)
         return pfb_internal_fail(PFB_E_INVALID, "cannot open the tuning cache for writing");
-    std::fprintf(f, "%s %d %d %d %d %lld path=%d fir_cpt=%d fir_sb=%d fused_sb=%d chunk_mib=%d ms=%.5f\n",
+    std::fprintf(f, "%s %d %d %d %d %lld path=%d fir_cpt=%d fir_sb=%d fused_sb=%d chunk_mib=%d bwd_sb=%d ms=%.5f\n",
                  device_arch_name().c_str(), d.dtype, d.channels, d.taps, d.batch, (long long)d.spectra, best.path,
-                 best.fir_cpt, best.fir_sb, best.fused_sb, best.chunk_mib, best_t);
+                 best.fir_cpt, best.fir_sb, best.fused_sb, best.chunk_mib, best.bwd_sb, best_t);
     std::fclose(f);
     return PFB_OK;
 }

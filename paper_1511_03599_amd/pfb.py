@@ -198,6 +198,52 @@ class Plan:
             pass
 
 
+class BatchedPlan:
+    """Many independent single-stream beams (complex64), each with its own
+    (C, T, S), run by one persistent kernel launch per call."""
+
+    def __init__(self, beams):
+        """beams: list of (C, T, S) tuples."""
+        self.beams = [(int(C), int(T), int(S)) for (C, T, S) in beams]
+        n = len(self.beams)
+        arr = (Desc * n)(*[make_desc(C, T, S, 1, "c64", 0) for (C, T, S) in self.beams])
+        h = ctypes.c_void_p()
+        check(lib().pfb_plan_create_batched(n, arr, ctypes.byref(h)))
+        self._h = h
+
+    def execute(self, xs, hs, Ys=None, stream=None):
+        n = len(self.beams)
+        if len(xs) != n or len(hs) != n:
+            raise PFBError(PFB_E_INVALID, "one x and one taps tensor per beam")
+        if Ys is None:
+            Ys = [torch.empty((S, C), dtype=torch.complex64, device=xs[0].device)
+                  for (C, T, S) in self.beams]
+        for (C, T, S), x, h, Y in zip(self.beams, xs, hs, Ys):
+            if x.dtype != torch.complex64 or tuple(x.shape[-2:]) != (S + T - 1, C) or not x.is_contiguous():
+                raise PFBError(PFB_E_INVALID, f"beam x must be contiguous complex64 [{S + T - 1}, {C}]")
+            if h.dtype != torch.float32 or tuple(h.shape) != (T, C) or not h.is_contiguous():
+                raise PFBError(PFB_E_INVALID, f"beam taps must be contiguous float32 [{T}, {C}]")
+            if Y.dtype != torch.complex64 or Y.numel() != S * C or not Y.is_contiguous():
+                raise PFBError(PFB_E_INVALID, f"beam Y must be contiguous complex64 [{S}, {C}]")
+        P = ctypes.c_void_p * n
+        xa = P(*[x.data_ptr() for x in xs])
+        ha = P(*[h.data_ptr() for h in hs])
+        Ya = P(*[Y.data_ptr() for Y in Ys])
+        check(lib().pfb_execute_batched(self._h, xa, ha, Ya, _stream(stream)))
+        return Ys
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pfb_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 _plan_cache: dict = {}
 
 
