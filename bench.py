@@ -5,14 +5,17 @@ already resident in HBM: the forward filter bank (ingest + convert, FIR, FFT,
 write) followed by its adjoint (inverse FFT, sample gradient, tap gradient).
 Workload: one stream of 65536 filtered spectra, C = 1024 channels, T = 16
 taps, complex64 Gaussian noise input, Hamming-windowed sinc taps (the
-tap-sweep workload of the paper's default channel count at 16 taps).
+tap-sweep workload at the paper's default channel count, at 16 taps).
 
 Prints ONE JSON line. `value` is the real-time sample rate in Msamples/s
-(new input samples B*S*C per second of fwd+bwd step). The same step on the
+(new input samples B*S*C per second of the fwd+bwd step). The same step on the
 plain comparator (unfused FIR launch then FFT launch, split adjoint) is timed
 beside it, and the oracle is timed on a bounded sample on the host cores.
+Unless --quick is given, `extras` adds the other workloads: the forward pass
+over T in {4..64}, the low-precision inputs, the 64-beam batched launch
+against 64 separate plain launches, and the 32-stream differentiable pass.
 
-    python bench.py [--steps K] [--warmup W] [--taps T] [--no-cpu] [--sweep]
+    python bench.py [--steps K] [--warmup W] [--no-cpu] [--quick]
 """
 from __future__ import annotations
 
@@ -44,10 +47,11 @@ def source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(kernel: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when there is none or the kernel sources changed since."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}.txt")
+def read_traffic(name: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    profiles/traffic_<name>.txt, or None when there is none or the kernel
+    sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{name}.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -58,12 +62,14 @@ def read_traffic(kernel: str):
     if kv.get("source_digest") != source_digest():
         return None
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv["hbm_bytes_per_call"])
     except (KeyError, ValueError):
         return None
 
 
 def time_calls(fn, n, stream):
+    """Average ms per call of fn over n back-to-back calls, HIP events on the
+    stream the library launches on."""
     import torch
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
@@ -72,14 +78,12 @@ def time_calls(fn, n, stream):
         fn()
     end.record(stream)
     end.synchronize()
-    return start.elapsed_time(end) / n  # ms
+    return start.elapsed_time(end) / n
 
 
 def cpu_baseline(C, T, rows_sample, seed):
     """The oracle (plain FP64 C, OpenMP) on a bounded sample of the same
     workload: forward and adjoint of `rows_sample` spectra of one stream."""
-    import numpy as np
-
     import oracle
     from paper_1511_03599_amd import synth
     st = synth.noise_stream(1, C, T, rows_sample, seed)
@@ -90,11 +94,120 @@ def cpu_baseline(C, T, rows_sample, seed):
     oracle.pfb_forward(st.x, st.h)
     oracle.pfb_adjoint(st.x, st.h, gY)
     dt = time.perf_counter() - t0
-    del np
-    return {"value": rows_sample * C / dt / 1e6, "unit": "Msamples/s", "cores": oracle.num_threads(),
+    return {"value": round(rows_sample * C / dt / 1e6, 3), "unit": "Msamples/s", "cores": oracle.num_threads(),
             "kind": "oracle",
             "sample": f"forward + adjoint of {rows_sample} spectra of the C={C}, T={T} stream "
-                      f"(FP64 direct FIR and O(C^2) DFT), {dt:.1f} s"}
+                      f"(FP64 direct FIR and O(C^2) DFT): {dt:.1f} s"}
+
+
+def extras_sweep(dev, stream, C, S):
+    import torch
+    from paper_1511_03599_amd import metrics, pfb, synth
+    out = {}
+    Y = torch.empty((1, S, C), dtype=torch.complex64, device=dev)
+    for T in (4, 8, 16, 32, 64):
+        st = synth.noise_stream(1, C, T, S, synth.seed_for(2, T), fast=True)
+        x = torch.view_as_complex(torch.from_numpy(st.x)).to(dev).contiguous()
+        h = torch.from_numpy(st.h).to(dev)
+        p = pfb.Plan(C, T, S, 1, "c64")
+        pf = pfb.Plan(C, T, S, 1, "c64", pfb.FIR_ONLY)
+        for _ in range(3):
+            p.execute(x, h, Y=Y)
+            pf.execute(x, h, y=Y)
+        tp = time_calls(lambda: p.execute(x, h, Y=Y), 20, stream)
+        tf = time_calls(lambda: pf.execute(x, h, y=Y), 20, stream)
+        out[str(T)] = {
+            "pfb_ms": round(tp, 5), "pfb_msamples_s": round(S * C / tp / 1e3, 1),
+            "pfb_gbs": round(metrics.pfb_fused_bytes(1, S, C, T) / tp / 1e6, 1), "path": p.info()["path"],
+            "fir_ms": round(tf, 5), "fir_gbs": round(metrics.fir_bytes(1, S, C, T) / tf / 1e6, 1),
+            "fir_gflops": round(metrics.effective_flops(S, C, T) / tf / 1e6, 1),
+            "fir_frac_valu": round(metrics.effective_flops(S, C, T) / tf / 1e9 / metrics.FP32_VALU_PEAK_TFLOPS, 4)}
+        del x, p, pf
+    return out
+
+
+def extras_precision(dev, stream):
+    """C=4096, T=16, 32768 spectra in each input type: FIR alone and the
+    whole filter bank; bytes use each type's sample size."""
+    import numpy as np
+    import torch
+    from paper_1511_03599_amd import metrics, pfb, synth
+    C, T, S = 4096, 16, 32768
+    out = {}
+    Y = torch.empty((1, S, C), dtype=torch.complex64, device=dev)
+    for dt in ("ci8", "ci16", "cf16", "c64"):
+        if dt == "c64":
+            st = synth.noise_stream(1, C, T, S, synth.seed_for(3, 3), fast=True)
+            x = torch.view_as_complex(torch.from_numpy(st.x)).to(dev).contiguous()
+        else:
+            st = synth.noise_stream(1, C, T, S, synth.seed_for(3, {"ci8": 0, "ci16": 1, "cf16": 2}[dt]), dtype=dt)
+            x = torch.from_numpy(np.ascontiguousarray(st.x)).to(dev)
+        h = torch.from_numpy(st.h).to(dev)
+        p = pfb.Plan(C, T, S, 1, dt)
+        pf = pfb.Plan(C, T, S, 1, dt, pfb.FIR_ONLY)
+        for _ in range(3):
+            p.execute(x, h, Y=Y)
+            pf.execute(x, h, y=Y)
+        tp = time_calls(lambda: p.execute(x, h, Y=Y), 10, stream)
+        tf = time_calls(lambda: pf.execute(x, h, y=Y), 10, stream)
+        out[dt] = {"pfb_ms": round(tp, 4), "pfb_msamples_s": round(S * C / tp / 1e3, 1),
+                   "pfb_gbs": round(metrics.pfb_fused_bytes(1, S, C, T, dt) / tp / 1e6, 1),
+                   "fir_ms": round(tf, 4), "fir_gbs": round(metrics.fir_bytes(1, S, C, T, dt) / tf / 1e6, 1),
+                   "conversions_per_s": round(2 * (S + T - 1) * C / tf / 1e6, 1), "path": p.info()["path"]}
+        del x, p, pf
+    return out
+
+
+def extras_batched(dev, stream):
+    """64 beams of uneven C, T, S: one persistent launch vs 64 separate plain
+    launches on one stream."""
+    import torch
+    from paper_1511_03599_amd import metrics, pfb, synth
+    beams = synth.beam_table()
+    desc = [(b.C, b.T, b.S) for b in beams]
+    xs = [synth.device_noise((b.S + b.T - 1, b.C), b.seed, dev) for b in beams]
+    hs = [torch.from_numpy(synth.windowed_sinc_taps(b.C, b.T)).to(dev) for b in beams]
+    Ys = [torch.empty((b.S, b.C), dtype=torch.complex64, device=dev) for b in beams]
+    bp = pfb.BatchedPlan(desc)
+    for _ in range(2):
+        bp.execute(xs, hs, Ys)
+    tb = time_calls(lambda: bp.execute(xs, hs, Ys), 5, stream)
+    del bp
+    plains = [pfb.Plan(C, T, S, 1, "c64", pfb.PLAIN) for (C, T, S) in desc]
+
+    def run_plain():
+        for p, x, h, Y in zip(plains, xs, hs, Ys):
+            p.execute(x[None], h, Y=Y[None])
+    run_plain()
+    tpl = time_calls(run_plain, 3, stream)
+    samples = sum(S * C for (C, T, S) in desc)
+    fused_bytes = sum(metrics.pfb_fused_bytes(1, S, C, T) for (C, T, S) in desc)
+    return {"beams": len(desc), "msamples": round(samples / 1e6, 1), "ms": round(tb, 3),
+            "msamples_s": round(samples / tb / 1e3, 1), "gbs": round(fused_bytes / tb / 1e6, 1),
+            "frac_hbm": round(fused_bytes / tb / 1e6 / HBM_PEAK, 4),
+            "plain_64_launches_ms": round(tpl, 3), "speedup_vs_plain": round(tpl / tb, 3)}
+
+
+def extras_differentiable(dev, stream):
+    """32 streams x 8192 spectra, C=1024, T=16: forward, adjoint, and both."""
+    import torch
+    from paper_1511_03599_amd import metrics, pfb, synth
+    B, S, C, T = 32, 8192, 1024, 16
+    x = synth.device_noise((B, S + T - 1, C), synth.seed_for(5, 1), dev)
+    h = torch.from_numpy(synth.windowed_sinc_taps(C, T)).to(dev)
+    gY = synth.device_noise((B, S, C), synth.seed_for(5, 2), dev)
+    Y = torch.empty((B, S, C), dtype=torch.complex64, device=dev)
+    gx = torch.empty_like(x)
+    gh = torch.empty((T, C), dtype=torch.float32, device=dev)
+    p = pfb.Plan(C, T, S, B, "c64")
+    for _ in range(2):
+        p.execute(x, h, Y=Y)
+        p.backward(x, h, gY, gx=gx, gh=gh)
+    tf = time_calls(lambda: p.execute(x, h, Y=Y), 10, stream)
+    tb = time_calls(lambda: p.backward(x, h, gY, gx=gx, gh=gh), 10, stream)
+    fb, bb = metrics.pfb_fused_bytes(B, S, C, T), metrics.backward_fused_bytes(B, S, C, T)
+    return {"fwd_ms": round(tf, 4), "bwd_ms": round(tb, 4), "fwd_gbs": round(fb / tf / 1e6, 1),
+            "bwd_gbs": round(bb / tb / 1e6, 1), "fwd_bwd_msamples_s": round(B * S * C / (tf + tb) / 1e3, 1)}
 
 
 def main():
@@ -106,18 +219,18 @@ def main():
     ap.add_argument("--channels", type=int, default=1024)
     ap.add_argument("--spectra", type=int, default=65536)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=12288)
-    ap.add_argument("--sweep", action="store_true", help="also time the forward pass for T in 4..64")
+    ap.add_argument("--cpu-rows", type=int, default=49152)
+    ap.add_argument("--quick", action="store_true", help="only the headline step")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with three plain 512 MiB device copies (counter calibration for profiles)")
     args = ap.parse_args()
 
     ws = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or ws > 1:
-        print("bench.py runs on one GPU: the filter bank here is a single-GPU build "
-              "(streams or beams would shard across GPUs with no communication); "
-              "run it with --gpus 1.", file=sys.stderr)
+        print("bench.py runs on one GPU: this filter bank is a single-GPU build (streams and beams "
+              "would shard across GPUs with no communication); run it with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_1511_03599_amd import metrics, pfb, synth
@@ -128,9 +241,7 @@ def main():
     st = synth.noise_stream(B, C, T, S, synth.seed_for(2, T), fast=True)
     x = torch.view_as_complex(torch.from_numpy(st.x)).to(dev).contiguous()
     h = torch.from_numpy(st.h).to(dev)
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(synth.seed_for(2, 100 + T))
-    gY = torch.randn((B, S, C), dtype=torch.complex64, device=dev, generator=gen)
+    gY = synth.device_noise((B, S, C), synth.seed_for(2, 100 + T), dev)
     Y = torch.empty((B, S, C), dtype=torch.complex64, device=dev)
     gx = torch.empty((B, S + T - 1, C), dtype=torch.complex64, device=dev)
     gh = torch.empty((T, C), dtype=torch.float32, device=dev)
@@ -143,7 +254,8 @@ def main():
         p.execute(x, h, Y=Y)
         p.backward(x, h, gY, gx=gx, gh=gh)
 
-    log(f"bench: plan {plan.info()}")
+    info = plan.info()
+    log(f"bench: plan {info}")
     for _ in range(args.warmup):
         step(plan)
     torch.cuda.synchronize()
@@ -151,7 +263,7 @@ def main():
     torch.cuda.synchronize()
     log(f"bench: step {t_step:.4f} ms")
 
-    # per-pass times (same stream, HIP events)
+    # per-call times of the two halves (same stream, HIP events)
     t_fwd = time_calls(lambda: plan.execute(x, h, Y=Y), args.steps, stream)
     t_bwd = time_calls(lambda: plan.backward(x, h, gY, gx=gx, gh=gh), args.steps, stream)
     for _ in range(args.warmup):
@@ -167,53 +279,57 @@ def main():
     value = samples / (t_step * 1e-3) / 1e6
     step_gbs = (fwd_bytes + bwd_bytes) / (t_step * 1e-3) / 1e9
 
-    # the forward pass is one kernel launch (fused FIR+FFT)
-    info = plan.info()
-    fwd_kernel = "pfb_fused_fwd" if info["path"] == "fused" else "pfb_split_fwd"
-    achieved = fwd_bytes / (t_fwd * 1e-3) / 1e9
-    traffic = read_traffic(f"{fwd_kernel}_c{C}_t{T}")
+    # dominant kernel of the step: the adjoint (one fused kernel plus the
+    # small fixed-order tap-gradient reduction) or the fused forward kernel
+    if t_bwd >= t_fwd:
+        name = "fused_bwd_kernel+gh_reduce_kernel" if info["backward_fused"] else "split_adjoint"
+        t_dom, b_dom, tkey = t_bwd, bwd_bytes, f"pfb_backward_c{C}_t{T}_s{S}"
+    else:
+        name = "fused_fwd_kernel" if info["path"] == "fused" else "split_forward"
+        t_dom, b_dom, tkey = t_fwd, fwd_bytes, f"pfb_execute_c{C}_t{T}_s{S}"
+    achieved = b_dom / (t_dom * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK, 4), "traffic": traffic, "kernel": fwd_kernel,
-            "algorithmic_bytes_per_launch": fwd_bytes, "launch_ms": round(t_fwd, 5)}
+            "frac": round(achieved / HBM_PEAK, 4), "traffic": read_traffic(tkey), "kernel": name,
+            "algorithmic_bytes_per_launch": b_dom, "launch_ms": round(t_dom, 5)}
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "Msamples/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t_step, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"pfb fwd+bwd, 1 stream x {S} spectra, C={C}, T={T}, complex64 noise",
-                   "channels": C, "taps": T, "spectra": S, "streams": B, "path": info["path"]},
+        "config": {"workload": f"pfb fwd+bwd, {B} stream x {S} spectra, C={C}, T={T}, complex64 noise",
+                   "channels": C, "taps": T, "spectra": S, "streams": B, "path": info["path"],
+                   "backward_fused": info["backward_fused"]},
         "hbm_gbs": round(step_gbs, 1), "hbm_frac": round(step_gbs / HBM_PEAK, 4),
         "fwd_ms": round(t_fwd, 5), "bwd_ms": round(t_bwd, 5),
-        "fwd_msamples_s": round(samples / (t_fwd * 1e-3) / 1e6, 1),
+        "fwd_gbs": round(fwd_bytes / t_fwd / 1e6, 1), "bwd_gbs": round(bwd_bytes / t_bwd / 1e6, 1),
         "plain": {"ms_per_step": round(t_plain, 5), "value": round(samples / (t_plain * 1e-3) / 1e6, 1),
                   "fwd_ms": round(t_plain_fwd, 5), "speedup": round(t_plain / t_step, 3)},
         "roofline": roof,
     }
+    del plain
 
-    if args.sweep:
-        sweep = {}
-        for Ts in (4, 8, 16, 32, 64):
-            sts = synth.noise_stream(1, C, Ts, S, synth.seed_for(2, Ts), fast=True)
-            xs = torch.view_as_complex(torch.from_numpy(sts.x)).to(dev).contiguous()
-            hs = torch.from_numpy(sts.h).to(dev)
-            ps = pfb.Plan(C, Ts, S, 1, "c64")
-            pf = pfb.Plan(C, Ts, S, 1, "c64", pfb.FIR_ONLY)
-            yy = torch.empty((1, S, C), dtype=torch.complex64, device=dev)
-            for _ in range(3):
-                ps.execute(xs, hs, Y=Y)
-                pf.execute(xs, hs, y=yy)
-            tf = time_calls(lambda: ps.execute(xs, hs, Y=Y), 20, stream)
-            tfir = time_calls(lambda: pf.execute(xs, hs, y=yy), 20, stream)
-            sweep[str(Ts)] = {
-                "pfb_ms": round(tf, 5), "pfb_msamples_s": round(S * C / tf / 1e3, 1),
-                "pfb_gbs": round(metrics.pfb_fused_bytes(1, S, C, Ts) / tf / 1e6, 1),
-                "fir_ms": round(tfir, 5),
-                "fir_gbs": round(metrics.fir_bytes(1, S, C, Ts) / tfir / 1e6, 1),
-                "fir_gflops": round(metrics.effective_flops(S, C, Ts) / tfir / 1e6, 1),
-                "path": ps.info()["path"]}
-            del xs, ps, pf, yy
-        out["sweep"] = sweep
+    if not args.quick:
+        log("bench: tap sweep")
+        extras = {"tap_sweep_c1024_s65536": extras_sweep(dev, stream, C, S)}
+        del x, gx, gY, Y
+        torch.cuda.empty_cache()
+        log("bench: low-precision inputs")
+        extras["precision_c4096_t16_s32768"] = extras_precision(dev, stream)
+        torch.cuda.empty_cache()
+        log("bench: batched beams")
+        extras["batched_64_beams"] = extras_batched(dev, stream)
+        torch.cuda.empty_cache()
+        log("bench: differentiable workload")
+        extras["differentiable_b32_s8192_c1024_t16"] = extras_differentiable(dev, stream)
+        out["extras"] = extras
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 26, dtype=torch.complex64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
 
     if not args.no_cpu:
         log("bench: timing the oracle on the host")

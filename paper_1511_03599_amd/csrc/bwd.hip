@@ -91,22 +91,45 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_bwd_kernel(BwdArgs a
 
     const int gid = t / G;
     const int lane = t % G;
+    // First-pass inputs of the next transform round, loaded one round ahead
+    // (the loads of a chunk's first round are in flight during the previous
+    // chunk's gradient phase) where registers allow: with two channels per
+    // thread the window, taps and tap-gradient sums leave no room, and the
+    // loads are issued at the start of each round instead. Rows outside
+    // [0, S) transform zeros.
+    constexpr int E = S::E;
+    constexpr bool AHEAD = CPT == 1;
+    float2 gv[E];
+    auto gather = [&](int base_, int round_) {
+        const int r = round_ * F::NG + gid;
+        const int64_t q = q0 + base_ + r;
+        if (base_ < nq && q >= 0 && q < a.S && base_ + r < nq) {
+            const float2 *src = gYb + q * C;
+            fft_gather_first<LOG2C, G, true>(lane, [&](int idx) { return src[idx]; }, gv);
+        } else {
+            sfor<E>([&](auto e) PFB_INLINE { gv[e] = make_float2(0.0f, 0.0f); });
+        }
+    };
+    if constexpr (AHEAD)
+        gather(0, 0);
     for (int base = 0; base < nq; base += RB) {
         // 1. inverse FFT of gY rows q0+base .. q0+base+RB-1 into LDS
 #pragma unroll 1
         for (int round = 0; round < F::ROUNDS; ++round) {
-            const int r = round * F::NG + gid;
-            const int64_t q = q0 + base + r;
-            float2 *row = lds + r * S::PADDED;
-            if (q >= 0 && q < a.S && base + r < nq) {
-                const float2 *src = gYb + q * C;
-                fft_run<LOG2C, G, true, false>(
-                    lane, row, a.tw, [&](int idx) { return src[idx]; },
-                    [&](int idx, float2 v) { row[S::pad(idx)] = v; });
+            float2 cur[E];
+            if constexpr (AHEAD) {
+                sfor<E>([&](auto e) PFB_INLINE { cur[e] = gv[e]; });
+                if (round + 1 < F::ROUNDS)
+                    gather(base, round + 1);
+                else
+                    gather(base + RB, 0);
             } else {
-                for (int i = lane; i < C; i += G)
-                    row[S::pad(i)] = make_float2(0.0f, 0.0f);
+                gather(base, round);
+                sfor<E>([&](auto e) PFB_INLINE { cur[e] = gv[e]; });
             }
+            float2 *row = lds + (round * F::NG + gid) * S::PADDED;
+            fft_passes<LOG2C, G, true, false>(lane, row, a.tw, cur,
+                                              [&](int idx, float2 v) { row[S::pad(idx)] = v; });
         }
         __syncthreads();
         // 2. sample gradient and tap-gradient partials

@@ -135,18 +135,39 @@ template <int LOG2C, int G> struct FftShape {
     static constexpr int pass_offset(int p) { return SCHED.pass_offset(p); }
 };
 
-// Run one transform. `src(idx)` returns input element idx (first pass);
-// `dst(idx, v)` receives output element idx (last pass). When SRC_IN_LDS the
-// first pass reads this group's own LDS row (so in a multi-wave group the
-// lanes synchronise before overwriting it). INV selects exp(+...).
-template <int LOG2C, int G, bool INV, bool SRC_IN_LDS, class Src, class Dst>
-__device__ __forceinline__ void fft_run(int lane, float2 *lds, const float2 *__restrict__ tw, Src &&src,
-                                        Dst &&dst)
+// First-pass inputs of one transform, gathered into the lane's registers in
+// the order the first pass consumes them: element j + i*C/R of butterfly
+// j = lane + G*q goes to v[q*R + i]. Split from the passes so that a caller
+// can issue these loads early and overlap their latency with other work.
+template <int LOG2C, int G, bool INV, class Src>
+__device__ __forceinline__ void fft_gather_first(int lane, Src &&src, float2 (&v)[FftShape<LOG2C, G>::E])
+{
+    using S = FftShape<LOG2C, G>;
+    constexpr int R = S::radix(0);
+    constexpr int NB = S::E / R;
+    constexpr int CR = S::C / R;
+    sfor<NB>([&](auto q) PFB_INLINE {
+        const int j = lane + G * decltype(q)::value;
+        sfor<R>([&](auto i) PFB_INLINE {
+            float2 t = src(j + decltype(i)::value * CR);
+            if constexpr (INV)
+                t = conj2(t);
+            v[decltype(q)::value * R + decltype(i)::value] = t;
+        });
+    });
+}
+
+// The passes of one transform whose first-pass inputs are already in v (see
+// fft_gather_first); `dst(idx, v)` receives output element idx from the last
+// pass. When SRC_IN_LDS the inputs were read from this group's own LDS row,
+// so a multi-wave group synchronises before overwriting it.
+template <int LOG2C, int G, bool INV, bool SRC_IN_LDS, class Dst>
+__device__ __forceinline__ void fft_passes(int lane, float2 *lds, const float2 *__restrict__ tw,
+                                           float2 (&v)[FftShape<LOG2C, G>::E], Dst &&dst)
 {
     using S = FftShape<LOG2C, G>;
     constexpr int C = S::C;
     constexpr int E = S::E;
-    float2 v[E];
     // Opaque copy of the twiddle pointer: keeps the compiler from hoisting
     // the twiddle loads of every pass out of a caller's loop over rows, which
     // would hold them all in registers at once.
@@ -160,22 +181,15 @@ __device__ __forceinline__ void fft_run(int lane, float2 *lds, const float2 *__r
         constexpr int NB = E / R;
         constexpr int CR = C / R;
 
-        // gather
-        sfor<NB>([&](auto q) PFB_INLINE {
-            const int j = lane + G * decltype(q)::value;
-            sfor<R>([&](auto i) PFB_INLINE {
-                const int idx = j + decltype(i)::value * CR;
-                float2 t;
-                if constexpr (P == 0) {
-                    t = src(idx);
-                    if constexpr (INV)
-                        t = conj2(t);
-                } else {
-                    t = lds[S::pad(idx)];
-                }
-                v[decltype(q)::value * R + decltype(i)::value] = t;
+        // gather (the first pass's inputs are already in v)
+        if constexpr (P > 0) {
+            sfor<NB>([&](auto q) PFB_INLINE {
+                const int j = lane + G * decltype(q)::value;
+                sfor<R>([&](auto i) PFB_INLINE {
+                    v[decltype(q)::value * R + decltype(i)::value] = lds[S::pad(j + decltype(i)::value * CR)];
+                });
             });
-        });
+        }
         if constexpr (G > 64 && P < S::NPASS - 1 && (P > 0 || SRC_IN_LDS))
             group_sync<G>(); // every lane has read before any lane overwrites
 
@@ -220,6 +234,18 @@ __device__ __forceinline__ void fft_run(int lane, float2 *lds, const float2 *__r
             group_sync<G>();
         }
     });
+}
+
+// Run one transform. `src(idx)` returns input element idx (first pass);
+// `dst(idx, v)` receives output element idx (last pass). When SRC_IN_LDS the
+// first pass reads this group's own LDS row. INV selects exp(+...).
+template <int LOG2C, int G, bool INV, bool SRC_IN_LDS, class Src, class Dst>
+__device__ __forceinline__ void fft_run(int lane, float2 *lds, const float2 *__restrict__ tw, Src &&src,
+                                        Dst &&dst)
+{
+    float2 v[FftShape<LOG2C, G>::E];
+    fft_gather_first<LOG2C, G, INV>(lane, src, v);
+    fft_passes<LOG2C, G, INV, SRC_IN_LDS>(lane, lds, tw, v, dst);
 }
 
 // Lanes per transform: C <= 1024 lives in one wave (or part of one); larger C

@@ -193,6 +193,16 @@ def noise_stream(B, C, T, S, seed, dtype="c64", fast=False) -> Stream:
     return Stream(quantise(xc, dtype), windowed_sinc_taps(C, T), dtype, B, S, C, T)
 
 
+def device_noise(shape, seed: int, device):
+    """Unit-variance complex64 Gaussian noise generated on the device with a
+    seeded torch generator (for timing runs whose sizes make host generation
+    slow; the values play no role in the timing)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    return torch.randn(tuple(shape), dtype=torch.complex64, device=device, generator=g)
+
+
 def tone_params(B: int, C: int, seed: int):
     """Per-stream off-centre tones: bin k_b uniform in [0, C), offset delta_b
     uniform in +-[0.1, 0.4] bins, phase uniform in [0, 2 pi)."""
