@@ -67,93 +67,74 @@ __device__ __forceinline__ float2 h2f(uint32_t w)
     return __half22float2(h);
 }
 
-template <int DT, int V> struct Loader;
-
-template <int V> struct Loader<DT_C64, V> {
-    static __device__ __forceinline__ void load(const void *base, int64_t i, float2 (&o)[V])
-    {
-        const float2 *p = reinterpret_cast<const float2 *>(base) + i;
-        if constexpr (V == 1) {
-            o[0] = *p;
-        } else if constexpr (V == 2) {
-            float4 q = *reinterpret_cast<const float4 *>(p);
-            o[0] = make_float2(q.x, q.y);
-            o[1] = make_float2(q.z, q.w);
-        } else {
-            float4 q0 = reinterpret_cast<const float4 *>(p)[0];
-            float4 q1 = reinterpret_cast<const float4 *>(p)[1];
-            o[0] = make_float2(q0.x, q0.y);
-            o[1] = make_float2(q0.z, q0.w);
-            o[2] = make_float2(q1.x, q1.y);
-            o[3] = make_float2(q1.z, q1.w);
-        }
-    }
+// A row fragment of V consecutive samples as loaded, still in the storage
+// type: prefetched rows are held packed (one 32-bit word per int16/fp16
+// sample, one per two int8 samples) and converted when they enter the
+// filter window, so each sample is still converted exactly once.
+template <int DT, int V> struct Packed {
+    static constexpr int WORDS = (V * SampleBytes<DT>::value + 3) / 4;
+    uint32_t w[WORDS];
 };
 
-template <int V> struct Loader<DT_CI16, V> {
-    static __device__ __forceinline__ void load(const void *base, int64_t i, float2 (&o)[V])
-    {
-        const uint32_t *p = reinterpret_cast<const uint32_t *>(base) + i;
-        uint32_t w[V];
-        if constexpr (V == 1) {
-            w[0] = *p;
-        } else if constexpr (V == 2) {
-            uint2 q = *reinterpret_cast<const uint2 *>(p);
-            w[0] = q.x;
-            w[1] = q.y;
-        } else {
-            uint4 q = *reinterpret_cast<const uint4 *>(p);
-            w[0] = q.x;
-            w[1] = q.y;
-            w[2] = q.z;
-            w[3] = q.w;
-        }
+template <int DT, int V>
+__device__ __forceinline__ void load_packed(const void *base, int64_t i, Packed<DT, V> &p)
+{
+    constexpr int B = V * SampleBytes<DT>::value; // bytes
+    const char *a = reinterpret_cast<const char *>(base) + i * SampleBytes<DT>::value;
+    if constexpr (B == 2) {
+        p.w[0] = *reinterpret_cast<const uint16_t *>(a);
+    } else if constexpr (B == 4) {
+        p.w[0] = *reinterpret_cast<const uint32_t *>(a);
+    } else if constexpr (B == 8) {
+        const uint2 q = *reinterpret_cast<const uint2 *>(a);
+        p.w[0] = q.x;
+        p.w[1] = q.y;
+    } else {
+        static_assert(B % 16 == 0, "fragment size");
 #pragma unroll
-        for (int k = 0; k < V; ++k)
-            o[k] = make_float2(s16lo(w[k]), s16hi(w[k]));
-    }
-};
-
-template <int V> struct Loader<DT_CI8, V> {
-    static __device__ __forceinline__ void load(const void *base, int64_t i, float2 (&o)[V])
-    {
-        if constexpr (V == 1) {
-            const uint16_t *p = reinterpret_cast<const uint16_t *>(base) + i;
-            uint32_t w = *p;
-            o[0] = make_float2(s8b(w, 0), s8b(w, 1));
-        } else if constexpr (V == 2) {
-            const uint32_t *p = reinterpret_cast<const uint32_t *>(reinterpret_cast<const uint16_t *>(base) + i);
-            uint32_t w = *p;
-            o[0] = make_float2(s8b(w, 0), s8b(w, 1));
-            o[1] = make_float2(s8b(w, 2), s8b(w, 3));
-        } else {
-            const uint2 *p = reinterpret_cast<const uint2 *>(reinterpret_cast<const uint16_t *>(base) + i);
-            uint2 q = *p;
-            o[0] = make_float2(s8b(q.x, 0), s8b(q.x, 1));
-            o[1] = make_float2(s8b(q.x, 2), s8b(q.x, 3));
-            o[2] = make_float2(s8b(q.y, 0), s8b(q.y, 1));
-            o[3] = make_float2(s8b(q.y, 2), s8b(q.y, 3));
+        for (int k = 0; k < B / 16; ++k) {
+            const uint4 q = reinterpret_cast<const uint4 *>(a)[k];
+            p.w[4 * k] = q.x;
+            p.w[4 * k + 1] = q.y;
+            p.w[4 * k + 2] = q.z;
+            p.w[4 * k + 3] = q.w;
         }
     }
-};
+}
 
-template <int V> struct Loader<DT_CF16, V> {
+template <int DT, int V> __device__ __forceinline__ void zero_packed(Packed<DT, V> &p)
+{
+#pragma unroll
+    for (int k = 0; k < Packed<DT, V>::WORDS; ++k)
+        p.w[k] = 0u;
+}
+
+// Convert a packed fragment to float32 (exact for every storage type).
+template <int DT, int V>
+__device__ __forceinline__ void unpack(const Packed<DT, V> &p, float2 (&o)[V])
+{
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+        if constexpr (DT == DT_C64) {
+            o[k] = make_float2(__uint_as_float(p.w[2 * k]), __uint_as_float(p.w[2 * k + 1]));
+        } else if constexpr (DT == DT_CI16) {
+            o[k] = make_float2(s16lo(p.w[k]), s16hi(p.w[k]));
+        } else if constexpr (DT == DT_CF16) {
+            o[k] = h2f(p.w[k]);
+        } else {
+            const uint32_t w = p.w[k / 2];
+            o[k] = make_float2(s8b(w, 2 * (k % 2)), s8b(w, 2 * (k % 2) + 1));
+        }
+    }
+}
+
+// Load V consecutive samples starting at sample index i and convert them.
+template <int DT, int V> struct Loader {
     static __device__ __forceinline__ void load(const void *base, int64_t i, float2 (&o)[V])
     {
-        const uint32_t *p = reinterpret_cast<const uint32_t *>(base) + i;
-        if constexpr (V == 1) {
-            o[0] = h2f(*p);
-        } else if constexpr (V == 2) {
-            uint2 q = *reinterpret_cast<const uint2 *>(p);
-            o[0] = h2f(q.x);
-            o[1] = h2f(q.y);
-        } else {
-            uint4 q = *reinterpret_cast<const uint4 *>(p);
-            o[0] = h2f(q.x);
-            o[1] = h2f(q.y);
-            o[2] = h2f(q.z);
-            o[3] = h2f(q.w);
-        }
+        Packed<DT, V> p;
+        load_packed<DT, V>(base, i, p);
+        unpack<DT, V>(p, o);
     }
 };
 

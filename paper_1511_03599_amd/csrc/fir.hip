@@ -25,7 +25,7 @@
 namespace pfb {
 
 template <int DT, int TP, int CPT, int D, bool REV>
-__global__ __launch_bounds__(256) void fir_kernel(FirArgs a)
+__global__ __launch_bounds__(256, 2) void fir_kernel(FirArgs a)
 {
     // Consecutive waves take consecutive channel chunks, then consecutive
     // tiles, so the waves resident at any time sweep one narrow band of rows.

@@ -41,20 +41,23 @@ __device__ __forceinline__ void fir_wave_task(const FirArgs &a, int64_t gw)
     });
 
     const char *xb = reinterpret_cast<const char *>(a.x) + (int64_t)b * a.in_bstride * SampleBytes<DT>::value;
-    auto ld = [&](int64_t row, float2 (&o)[CPT]) {
-        if (active && row >= 0 && row < a.in_rows) {
-            Loader<DT, CPT>::load(xb, row * a.C + c0, o);
-        } else {
-            sfor<CPT>([&](auto k) PFB_INLINE { o[k] = make_float2(0.0f, 0.0f); });
-        }
+    auto ldp = [&](int64_t row, Packed<DT, CPT> &o) {
+        if (active && row >= 0 && row < a.in_rows)
+            load_packed<DT, CPT>(xb, row * a.C + c0, o);
+        else
+            zero_packed<DT, CPT>(o);
     };
 
     float2 w[TP][CPT];
-    float2 pf[D][CPT];
-    sfor<TP - 1>([&](auto j) PFB_INLINE { ld(row0 + j, w[j]); });
+    Packed<DT, CPT> pf[D]; // prefetched rows, still packed
+    sfor<TP - 1>([&](auto j) PFB_INLINE {
+        Packed<DT, CPT> t;
+        ldp(row0 + j, t);
+        unpack<DT, CPT>(t, w[j]);
+    });
     sfor<D>([&](auto k) PFB_INLINE {
         if (k < nout)
-            ld(row0 + TP - 1 + k, pf[k]);
+            ldp(row0 + TP - 1 + k, pf[k]);
     });
 
     float2 *yb = a.y + (int64_t)b * a.y_bstride + (s_begin - a.out_first) * a.C + c0;
@@ -63,9 +66,9 @@ __device__ __forceinline__ void fir_wave_task(const FirArgs &a, int64_t gw)
             constexpr int jj = decltype(jjc)::value;
             const int o = base + jj;
             if (o < nout) {
-                sfor<CPT>([&](auto k) PFB_INLINE { w[(jj + TP - 1) % TP][k] = pf[jj % D][k]; });
+                unpack<DT, CPT>(pf[jj % D], w[(jj + TP - 1) % TP]);
                 if (o + D < nout)
-                    ld(row0 + o + D + TP - 1, pf[jj % D]);
+                    ldp(row0 + o + D + TP - 1, pf[jj % D]);
                 float2 acc[CPT];
                 sfor<CPT>([&](auto k) PFB_INLINE {
                     float ar = 0.0f, ai = 0.0f;

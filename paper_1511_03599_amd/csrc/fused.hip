@@ -68,25 +68,24 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_fwd_kernel(FusedArgs
             hp[j][k] = (j >= off) ? a.h[(int64_t)(j - off) * C + c0 + k] : 0.0f;
 
     const char *xb = reinterpret_cast<const char *>(a.x) + (int64_t)b * in_rows * C * SampleBytes<DT>::value;
-    auto ld = [&](int64_t row, float2 (&o)[CPT]) {
-        if (row >= 0 && row < in_rows) {
-            Loader<DT, CPT>::load(xb, row * C + c0, o);
-        } else {
-#pragma unroll
-            for (int k = 0; k < CPT; ++k)
-                o[k] = make_float2(0.0f, 0.0f);
-        }
+    auto ldp = [&](int64_t row, Packed<DT, CPT> &o) {
+        if (row >= 0 && row < in_rows)
+            load_packed<DT, CPT>(xb, row * C + c0, o);
+        else
+            zero_packed<DT, CPT>(o);
     };
 
     float2 w[TP][CPT];
-    float2 pf[D][CPT];
-#pragma unroll
-    for (int j = 0; j < TP - 1; ++j)
-        ld(row0 + j, w[j]);
-#pragma unroll
-    for (int k = 0; k < D; ++k)
+    Packed<DT, CPT> pf[D]; // prefetched rows, still packed
+    sfor<TP - 1>([&](auto j) PFB_INLINE {
+        Packed<DT, CPT> t;
+        ldp(row0 + j, t);
+        unpack<DT, CPT>(t, w[j]);
+    });
+    sfor<D>([&](auto k) PFB_INLINE {
         if (k < nout)
-            ld(row0 + TP - 1 + k, pf[k]);
+            ldp(row0 + TP - 1 + k, pf[k]);
+    });
 
     const int gid = t / G;
     const int lane = t % G;
@@ -98,11 +97,9 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_fwd_kernel(FusedArgs
         for (int jj = 0; jj < RB; ++jj) {
             const int o = base + jj;
             if (o < nout) {
-#pragma unroll
-                for (int k = 0; k < CPT; ++k)
-                    w[(jj + TP - 1) % TP][k] = pf[jj % D][k];
+                unpack<DT, CPT>(pf[jj % D], w[(jj + TP - 1) % TP]);
                 if (o + D < nout)
-                    ld(row0 + o + D + TP - 1, pf[jj % D]);
+                    ldp(row0 + o + D + TP - 1, pf[jj % D]);
 #pragma unroll
                 for (int k = 0; k < CPT; ++k) {
                     float ar = 0.0f, ai = 0.0f;
