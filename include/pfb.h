@@ -153,10 +153,17 @@ pfb_status pfb_backward(pfb_plan *plan, const void *x, const float *taps, const 
 
 /*
  * Many independent beams with their own C, T, S (one stream each, complex
- * float32, C a power of two in [32, 8192]) in one persistent launch per
- * call, recorded once into a HIP graph on first execution.
+ * float32, C a power of two in [32, 8192], T <= 64) in one persistent launch
+ * per call, recorded into a HIP graph when the plan is created. Each beam's
+ * result is the forward filter bank of its descriptor (Alg. 1 then Eq. (2)),
+ * bit-identical to a separate single-beam plan.
  *   nbeams  >= 1; beams: host array of nbeams descriptors (batch must be 1,
  *           dtype C64; flags ignored)
+ * The plan owns its tile table and one slot of filtered spectra per
+ * persistent workgroup (about 1 MiB each with the default tile size, or the
+ * tuned one from the cache named by PFB_TUNE_CACHE). Errors:
+ * PFB_E_UNSUPPORTED for other dtypes or T > 64, PFB_E_NOMEM if the device
+ * allocations fail.
  */
 pfb_status pfb_plan_create_batched(int32_t nbeams, const pfb_desc *beams, pfb_plan **out);
 
@@ -179,6 +186,16 @@ pfb_status pfb_execute_batched(pfb_plan *plan, const void *const *x, const float
  * built-in defaults.
  */
 pfb_status pfb_tune(const pfb_desc *desc, const char *cache_path);
+
+/*
+ * Time the candidate tile sizes of a batched plan for this beam table (the
+ * same descriptors pfb_plan_create_batched takes; temporary buffers for every
+ * beam are allocated and freed inside this call) and append the fastest to
+ * the tuning cache file `cache_path`, keyed by the device, the beam count and
+ * the total sample count. Batched plans created afterwards read it from the
+ * cache named by PFB_TUNE_CACHE.
+ */
+pfb_status pfb_tune_batched(int32_t nbeams, const pfb_desc *beams, const char *cache_path);
 
 /* Report what a plan will run. */
 pfb_status pfb_plan_get_info(const pfb_plan *plan, pfb_plan_info *info);

@@ -1,26 +1,23 @@
 // Batched multi-beam filter bank: many independent beams, each with its own
 // C, T and S, processed by ONE persistent kernel launch per call.
 //
-// Work is a table of tiles built on the host when the plan is created:
-//   FIR tile: up to 8 wave tasks of one beam (a wave task is 64*CPT channels
-//             x 32 filtered spectra, the register-window FIR of fir.hip),
-//             writing the beam's filtered spectra into the plan's workspace;
-//   FFT tile: the C-point transforms of one group of rows of one beam,
-//             reading the filtered spectra back and writing the frequency
-//             spectra.
-// Rows of a beam are split into groups (about 2 MiB of filtered spectra each);
-// a group's FFT tile may start once all of its FIR tiles have finished. The
-// tile table is ordered beam by beam, largest beams first, with each group's
-// FFT tile placed after the FIR tiles of the NEXT group, so a transform
-// rarely waits and reads its rows back while they are still cached.
-//
-// The persistent workgroups take tiles in table order from an atomic counter.
-// A FIR tile publishes its completion with a release increment of its
-// group's counter; an FFT tile waits (bounded spin, acquire) for that counter
-// to reach the group's FIR tile count. Every tile a wait can depend on has a
-// smaller table index, so it was taken earlier by a workgroup that is already
-// running and never waits itself: the waits always end. A wait that exceeds
-// its bound (a library bug) raises an error flag instead of hanging.
+// Work is a table of tiles built on the host when the plan is created. A tile
+// is a run of consecutive filtered spectra of one beam, over all of its
+// channels. A persistent workgroup takes the next tile from an atomic counter
+// and does all of the tile's work itself:
+//   1. the register-window FIR of every channel of the tile's rows (wave
+//      tasks of 64*CPT channels x 32 rows spread over the workgroup's waves),
+//      written to the workgroup's own slot of filtered spectra;
+//   2. a workgroup barrier;
+//   3. the C-point transforms of the slot's rows, written to the beam's
+//      frequency spectra.
+// No tile depends on another, so no workgroup ever waits for another and no
+// device-scope fences are needed: those would write back or invalidate the
+// whole L2 of an XCD on every tile. The slot is reused tile after tile; it is
+// small enough that the filtered spectra mostly travel through the caches
+// rather than HBM. Tiles of one beam are consecutive in the table, so rows
+// shared by neighbouring tiles (the T-1 history rows) are read while still
+// cached. Beams are ordered by tile work, largest first.
 //
 // The counter reset and the persistent kernel are recorded once into a HIP
 // graph (explicit kernel nodes, no memset nodes) and replayed on each call.
@@ -45,12 +42,14 @@ constexpr int BT_THREADS = 512;          // threads per persistent workgroup
 constexpr int BT_WAVES = BT_THREADS / 64;
 constexpr int BT_TASK_ROWS = 32;         // filtered spectra per FIR wave task
 constexpr int BT_LDS = 8704;             // float2: the largest transform round
+constexpr int BT_MAX_TAPS = 64;
 
 struct BeamInfo {
-    float2 *yws;           // filtered spectra workspace of this beam [S][C]
     const float2 *tw;      // twiddles for C
     int C, T, TP, log2c, cpt;
-    int n_cchunks, n_tiles;
+    int n_cchunks;         // channel chunks of 64*cpt
+    int tile_rows;         // filtered spectra per tile
+    int pad;
     int64_t S;
 };
 
@@ -62,12 +61,10 @@ struct BeamPtrs {
 };
 
 struct TileDesc {
-    int kind;              // 0 FIR, 1 FFT
     int beam;
-    int64_t first;         // FIR: first wave task; FFT: first row
-    int count;             // FIR: wave tasks (<= 8); FFT: rows
-    int group;             // dependency counter
-    int need;              // FFT: FIR tiles of the group
+    int nrows;
+    int64_t row0;          // first filtered spectrum of the tile
+    int cls;               // tile class (bt_class of the beam's TP and C)
     int pad;
 };
 
@@ -76,53 +73,56 @@ struct BatchedArgs {
     const BeamPtrs *ptrs;
     const TileDesc *tiles;
     int *queue;            // next tile to take
-    int *deps;             // per-group finished FIR tiles
-    int *err;              // set when a wait exceeds its bound
+    float2 *slots;         // one slot of filtered spectra per workgroup
+    int64_t slot_elems;
     int ntiles;
-    int ngroups;
-    long long spin_limit;
 };
 
-__global__ __launch_bounds__(256) void batched_reset_kernel(BatchedArgs a)
+__global__ __launch_bounds__(64) void batched_reset_kernel(BatchedArgs a)
 {
-    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (i == 0) {
+    if (threadIdx.x == 0)
         *a.queue = 0;
-        *a.err = 0;
-    }
-    for (int g = i; g < a.ngroups; g += (int)(gridDim.x * blockDim.x))
-        a.deps[g] = 0;
 }
 
+// FIR shape per padded tap count, chosen so that the FIR and the largest
+// transform fit the register budget together: two channels per lane
+// (16-byte loads) for short windows, one otherwise; a shallower prefetch for
+// the longest window.
+constexpr int batched_cpt(int tp) { return tp <= 8 ? 2 : 1; }
+constexpr int batched_prefetch(int tp) { return tp >= 64 ? 4 : 8; }
+
+// FIR of every channel of rows [row0, row0 + nrows) of one beam into the
+// slot (row r of the tile at slot + r*C); this wave takes wave tasks
+// wave_id(), wave_id() + BT_WAVES, ...
 template <int TP, int CPT>
-__device__ __forceinline__ void batched_fir(const BeamInfo &bm, const BeamPtrs &bp, int64_t task)
+__device__ __forceinline__ void batched_fir(const BeamInfo bm, const void *x, const float *h, float2 *slot,
+                                         int64_t row0, int nrows)
 {
     FirArgs f{};
-    f.x = bp.x;
-    f.h = bp.h;
-    f.y = bm.yws;
+    f.x = x;
+    f.h = h;
+    f.y = slot;
     f.C = bm.C;
     f.T = bm.T;
     f.B = 1;
     f.SB = BT_TASK_ROWS;
-    f.n_tiles = bm.n_tiles;
+    f.n_tiles = (nrows + BT_TASK_ROWS - 1) / BT_TASK_ROWS;
     f.n_cchunks = bm.n_cchunks;
     f.in_rows = bm.S + bm.T - 1;
     f.in_bstride = 0;
     f.shift = TP - bm.T;
-    f.out_first = 0;
-    f.out_count = bm.S;
+    f.out_first = row0;
+    f.out_count = nrows;
     f.y_bstride = 0;
-    fir_wave_task<DT_C64, TP, CPT, 8, false>(f, task);
+    const int ntasks = f.n_tiles * f.n_cchunks;
+    for (int task = wave_id(); task < ntasks; task += BT_WAVES)
+        fir_wave_task<DT_C64, TP, CPT, batched_prefetch(TP), false, false>(f, task);
 }
 
-// The transform of each size is a separate (not inlined) device function:
-// merged into one body with the other sizes and the FIR variants, the
-// transforms spill heavily. The call costs one save and restore of the
-// callee-saved registers per tile.
+// The C-point transforms of the slot's first nrows rows into out (row r at
+// out + r*C).
 template <int LOG2C>
-__device__ __noinline__ void batched_fft(const BeamInfo &bm, const BeamPtrs &bp, int64_t row0, int nrows,
-                                         float2 *lds)
+__device__ __forceinline__ void batched_fft(const float2 *tw, const float2 *slot, float2 *out, int nrows, float2 *lds)
 {
     constexpr int C = 1 << LOG2C;
     constexpr int G = FftLanes<LOG2C>::G;
@@ -136,86 +136,99 @@ __device__ __noinline__ void batched_fft(const BeamInfo &bm, const BeamPtrs &bp,
         const bool valid = r < nrows;
         // a group past the last row repeats the last row without storing it
         const int rr = valid ? r : nrows - 1;
-        const float2 *in = bm.yws + (row0 + rr) * C;
-        float2 *out = bp.Y + (row0 + rr) * C;
+        const float2 *in = slot + (int64_t)rr * C;
+        float2 *o = out + (int64_t)rr * C;
         if constexpr (F == 1) {
             fft_run<LOG2C, G, false, false>(
-                lane, lds, bm.tw, [&](int idx) { return in[idx]; },
-                [&](int idx, float2 v) { store_nt(out + idx, v); });
+                lane, lds, tw, [&](int idx) { return in[idx]; }, [&](int idx, float2 v) { store_nt(o + idx, v); });
         } else if constexpr (G > 64) {
             // transforms span several waves and synchronise the block, so
             // every group runs the passes
             fft_run<LOG2C, G, false, false>(
-                lane, lds + gid * S::PADDED, bm.tw, [&](int idx) { return in[idx]; },
+                lane, lds + gid * S::PADDED, tw, [&](int idx) { return in[idx]; },
                 [&](int idx, float2 v) {
                     if (valid)
-                        store_nt(out + idx, v);
+                        store_nt(o + idx, v);
                 });
         } else if (valid) {
             fft_run<LOG2C, G, false, false>(
-                lane, lds + gid * S::PADDED, bm.tw, [&](int idx) { return in[idx]; },
-                [&](int idx, float2 v) { store_nt(out + idx, v); });
+                lane, lds + gid * S::PADDED, tw, [&](int idx) { return in[idx]; },
+                [&](int idx, float2 v) { store_nt(o + idx, v); });
         }
         __syncthreads(); // the LDS rows are reused by the next round
     }
 }
 
-__global__ __launch_bounds__(BT_THREADS) void batched_kernel(BatchedArgs a)
+// Tile classes: (padded taps, channels per lane) x transform size. Tiles of
+// one class are consecutive in the table.
+constexpr int fir_variant(int tp) { return tp == 4 ? 0 : tp == 8 ? 1 : tp == 16 ? 2 : tp == 32 ? 3 : 4; }
+constexpr int bt_class(int tp, int log2c) { return fir_variant(tp) * 9 + (log2c - 5); }
+
+// Takes tiles from the queue while they belong to class (TP, LOG2C) and does
+// their work; returns the first tile of another class (or ntiles when the
+// queue is drained). One call covers a whole run of same-class tiles, so the
+// cost of the call itself is paid a few times per workgroup, not per tile.
+template <int TP, int LOG2C>
+__device__ __noinline__ int batched_run(const BatchedArgs &a, float2 *slot, float2 *lds, int *s_tile, int t)
+{
+    constexpr int CPT = batched_cpt(TP);
+    const TileDesc *tiles = as_global(a.tiles);
+    slot = as_global(slot);
+    for (;;) {
+        const TileDesc td = tiles[t];
+        const BeamInfo bm = as_global(a.beams)[td.beam];
+        const BeamPtrs bp = as_global(a.ptrs)[td.beam];
+        batched_fir<TP, CPT>(bm, as_global(bp.x), as_global(bp.h), slot, td.row0, td.nrows);
+        // the slot's rows, written by every wave, are read back by others
+        __syncthreads();
+        batched_fft<LOG2C>(as_global(bm.tw), slot, as_global(bp.Y) + td.row0 * bm.C, td.nrows, lds);
+        // (batched_fft ends with a barrier: the slot and LDS are free again)
+        if (threadIdx.x == 0)
+            *s_tile = __hip_atomic_fetch_add(as_global(a.queue), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        t = *s_tile;
+        __syncthreads();
+        if (t >= a.ntiles || tiles[t].cls != bt_class(TP, LOG2C))
+            return t;
+    }
+}
+
+template <int TP>
+__device__ __forceinline__ int batched_dispatch_c(const BatchedArgs &a, float2 *slot, float2 *lds, int *s_tile, int t,
+                                                  int log2c)
+{
+    switch (log2c) {
+    case 5: return batched_run<TP, 5>(a, slot, lds, s_tile, t);
+    case 6: return batched_run<TP, 6>(a, slot, lds, s_tile, t);
+    case 7: return batched_run<TP, 7>(a, slot, lds, s_tile, t);
+    case 8: return batched_run<TP, 8>(a, slot, lds, s_tile, t);
+    case 9: return batched_run<TP, 9>(a, slot, lds, s_tile, t);
+    case 10: return batched_run<TP, 10>(a, slot, lds, s_tile, t);
+    case 11: return batched_run<TP, 11>(a, slot, lds, s_tile, t);
+    case 12: return batched_run<TP, 12>(a, slot, lds, s_tile, t);
+    default: return batched_run<TP, 13>(a, slot, lds, s_tile, t);
+    }
+}
+
+__global__ __launch_bounds__(BT_THREADS, 1) void batched_kernel(BatchedArgs a)
 {
     __shared__ float2 lds[BT_LDS];
     __shared__ int s_tile;
-    for (;;) {
-        if (threadIdx.x == 0)
-            s_tile = __hip_atomic_fetch_add(a.queue, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
-        const int t = s_tile;
-        __syncthreads();
-        if (t >= a.ntiles)
-            break;
-        const TileDesc td = a.tiles[t];
-        const BeamInfo bm = a.beams[td.beam];
-        const BeamPtrs bp = a.ptrs[td.beam];
-        if (td.kind == 0) {
-            const int w = wave_id();
-            if (w < td.count) {
-                const int64_t task = td.first + w;
-                switch (bm.TP) {
-                case 4: batched_fir<4, 1>(bm, bp, task); break;
-                case 8: batched_fir<8, 1>(bm, bp, task); break;
-                case 16: batched_fir<16, 1>(bm, bp, task); break;
-                default: batched_fir<32, 1>(bm, bp, task); break;
-                }
-            }
-            // publish: every thread's stores are made visible at device
-            // scope before the group counter moves
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            __syncthreads();
-            if (threadIdx.x == 0)
-                __hip_atomic_fetch_add(a.deps + td.group, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            if (threadIdx.x == 0) {
-                long long spins = 0;
-                while (__hip_atomic_load(a.deps + td.group, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < td.need) {
-                    __builtin_amdgcn_s_sleep(2);
-                    if (++spins > a.spin_limit) {
-                        __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        break;
-                    }
-                }
-            }
-            __syncthreads();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            switch (bm.log2c) {
-            case 5: batched_fft<5>(bm, bp, td.first, td.count, lds); break;
-            case 6: batched_fft<6>(bm, bp, td.first, td.count, lds); break;
-            case 7: batched_fft<7>(bm, bp, td.first, td.count, lds); break;
-            case 8: batched_fft<8>(bm, bp, td.first, td.count, lds); break;
-            case 9: batched_fft<9>(bm, bp, td.first, td.count, lds); break;
-            case 10: batched_fft<10>(bm, bp, td.first, td.count, lds); break;
-            case 11: batched_fft<11>(bm, bp, td.first, td.count, lds); break;
-            case 12: batched_fft<12>(bm, bp, td.first, td.count, lds); break;
-            default: batched_fft<13>(bm, bp, td.first, td.count, lds); break;
-            }
+    float2 *slot = a.slots + (int64_t)blockIdx.x * a.slot_elems;
+    if (threadIdx.x == 0)
+        s_tile = __hip_atomic_fetch_add(a.queue, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    int t = s_tile;
+    __syncthreads();
+    while (t < a.ntiles) {
+        const int cls = a.tiles[t].cls;
+        const int log2c = 5 + cls % 9;
+        switch (cls / 9) {
+        case 0: t = batched_dispatch_c<4>(a, slot, lds, &s_tile, t, log2c); break;
+        case 1: t = batched_dispatch_c<8>(a, slot, lds, &s_tile, t, log2c); break;
+        case 2: t = batched_dispatch_c<16>(a, slot, lds, &s_tile, t, log2c); break;
+        case 3: t = batched_dispatch_c<32>(a, slot, lds, &s_tile, t, log2c); break;
+        default: t = batched_dispatch_c<64>(a, slot, lds, &s_tile, t, log2c); break;
         }
     }
 }
@@ -233,11 +246,12 @@ struct Batched {
     BeamPtrs *h_ptrs = nullptr;         // pinned staging for the pointer table
     std::vector<BeamPtrs> last_ptrs;    // what the device table holds
     TileDesc *d_tiles = nullptr;
-    int *d_counters = nullptr;          // [0] queue, [1] err, [2..] deps
-    int *h_err = nullptr;               // pinned copy of the error flag
-    std::vector<void *> allocs;         // workspaces and twiddle tables
-    int ntiles = 0, ngroups = 0;
+    int *d_queue = nullptr;
+    float2 *d_slots = nullptr;
+    std::vector<void *> allocs;         // twiddle tables
+    int ntiles = 0;
     int grid = 0;
+    int64_t slot_elems = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;
@@ -257,13 +271,11 @@ void batched_free(Batched *b)
         (void)hipEventDestroy(b->done);
     for (void *p : b->allocs)
         (void)hipFree(p);
-    for (void *p : {(void *)b->d_info, (void *)b->d_ptrs, (void *)b->d_tiles, (void *)b->d_counters})
+    for (void *p : {(void *)b->d_info, (void *)b->d_ptrs, (void *)b->d_tiles, (void *)b->d_queue, (void *)b->d_slots})
         if (p)
             (void)hipFree(p);
     if (b->h_ptrs)
         (void)hipHostFree(b->h_ptrs);
-    if (b->h_err)
-        (void)hipHostFree(b->h_err);
     delete b;
 }
 
@@ -303,11 +315,22 @@ static pfb_status twiddle_table(int log2c, float2 **out)
     return PFB_OK;
 }
 
+// Filtered spectra per tile of a beam with C channels: about tile_kib KiB of
+// filtered spectra, a whole number of FIR wave tasks, at least one.
+static int batched_tile_rows(int C, int64_t S, int tile_kib)
+{
+    int64_t r = ((int64_t)tile_kib << 10) / ((int64_t)C * 8);
+    r = std::max<int64_t>(BT_TASK_ROWS, r / BT_TASK_ROWS * BT_TASK_ROWS);
+    const int64_t s_up = (S + BT_TASK_ROWS - 1) / BT_TASK_ROWS * BT_TASK_ROWS;
+    return (int)std::min<int64_t>(r, std::max<int64_t>(BT_TASK_ROWS, s_up));
+}
+
 static pfb_status build_batched(int32_t nbeams, const pfb_desc *beams, Batched *B)
 {
     B->nbeams = nbeams;
     B->descs.assign(beams, beams + nbeams);
     B->info.resize((size_t)nbeams);
+    const int tile_kib = batched_tile_kib(nbeams, beams);
     float2 *tw_by_log2c[14] = {};
     for (int i = 0; i < nbeams; ++i) {
         const pfb_desc &d = beams[i];
@@ -318,12 +341,11 @@ static pfb_status build_batched(int32_t nbeams, const pfb_desc *beams, Batched *
         while (bi.TP < d.taps)
             bi.TP *= 2;
         bi.log2c = ilog2_exact(d.channels);
-        // one channel per lane: the persistent kernel's register budget is
-        // the maximum over every tap count and transform size it serves
-        bi.cpt = 1;
+        bi.cpt = batched_cpt(bi.TP);
         bi.n_cchunks = (d.channels + 64 * bi.cpt - 1) / (64 * bi.cpt);
-        bi.n_tiles = (int)((d.spectra + BT_TASK_ROWS - 1) / BT_TASK_ROWS);
         bi.S = d.spectra;
+        bi.tile_rows = batched_tile_rows(d.channels, d.spectra, tile_kib);
+        bi.pad = 0;
         if (!tw_by_log2c[bi.log2c]) {
             pfb_status st = twiddle_table(bi.log2c, &tw_by_log2c[bi.log2c]);
             if (st != PFB_OK)
@@ -331,79 +353,36 @@ static pfb_status build_batched(int32_t nbeams, const pfb_desc *beams, Batched *
             B->allocs.push_back(tw_by_log2c[bi.log2c]);
         }
         bi.tw = tw_by_log2c[bi.log2c];
-        void *ws = nullptr;
-        if (hipMalloc(&ws, (size_t)d.spectra * d.channels * 8) != hipSuccess)
-            return pfb_internal_fail(PFB_E_NOMEM, "hipMalloc(batched filtered-spectra workspace)");
-        B->allocs.push_back(ws);
-        bi.yws = reinterpret_cast<float2 *>(ws);
+        B->slot_elems = std::max<int64_t>(B->slot_elems, (int64_t)bi.tile_rows * bi.C);
     }
 
-    // tile table: beams largest first; per beam, groups of rows
+    // tile table: beams by tile size, largest first; each beam's tiles in
+    // row order
     std::vector<int> order((size_t)nbeams);
     for (int i = 0; i < nbeams; ++i)
         order[(size_t)i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        return beams[a].spectra * beams[a].channels > beams[b].spectra * beams[b].channels;
+        const BeamInfo &x = B->info[(size_t)a], &y = B->info[(size_t)b];
+        const int64_t wx = (int64_t)x.tile_rows * x.C, wy = (int64_t)y.tile_rows * y.C;
+        if (wx != wy)
+            return wx > wy;
+        return bt_class(x.TP, x.log2c) < bt_class(y.TP, y.log2c);
     });
     std::vector<TileDesc> tiles;
-    int ngroups = 0;
     for (int bidx : order) {
         const BeamInfo &bi = B->info[(size_t)bidx];
-        // rows per group: about 2 MiB of filtered spectra, a multiple of the
-        // FIR task height
-        int64_t rg = ((int64_t)2 << 20) / ((int64_t)bi.C * 8);
-        rg = std::max<int64_t>(BT_TASK_ROWS, rg / BT_TASK_ROWS * BT_TASK_ROWS);
-        const int64_t ngr = (bi.S + rg - 1) / rg;
-        std::vector<TileDesc> pending_fft;
-        for (int64_t g = 0; g < ngr; ++g) {
-            const int64_t r0 = g * rg;
-            const int64_t nr = std::min<int64_t>(rg, bi.S - r0);
-            const int64_t t0 = r0 / BT_TASK_ROWS, t1 = (r0 + nr + BT_TASK_ROWS - 1) / BT_TASK_ROWS;
-            const int64_t task0 = t0 * bi.n_cchunks, task1 = t1 * bi.n_cchunks;
-            const int gid = ngroups++;
-            int nfir = 0;
-            for (int64_t k = task0; k < task1; k += BT_WAVES) {
-                TileDesc t{};
-                t.kind = 0;
-                t.beam = bidx;
-                t.first = k;
-                t.count = (int)std::min<int64_t>(BT_WAVES, task1 - k);
-                t.group = gid;
-                tiles.push_back(t);
-                ++nfir;
-            }
-            // transforms of the previous group follow this group's FIR tiles
-            for (const TileDesc &f : pending_fft)
-                tiles.push_back(f);
-            pending_fft.clear();
-            TileDesc f{};
-            f.kind = 1;
-            f.beam = bidx;
-            f.first = r0;
-            f.count = (int)nr;
-            f.group = gid;
-            f.need = nfir;
-            pending_fft.push_back(f);
+        for (int64_t r0 = 0; r0 < bi.S; r0 += bi.tile_rows) {
+            TileDesc t{};
+            t.beam = bidx;
+            t.row0 = r0;
+            t.nrows = (int)std::min<int64_t>(bi.tile_rows, bi.S - r0);
+            t.cls = bt_class(bi.TP, bi.log2c);
+            tiles.push_back(t);
         }
-        for (const TileDesc &f : pending_fft)
-            tiles.push_back(f);
     }
+    if (tiles.size() > (size_t)INT32_MAX - ((size_t)1 << 20))
+        return pfb_internal_fail(PFB_E_UNSUPPORTED, "batched tile table too large");
     B->ntiles = (int)tiles.size();
-    B->ngroups = ngroups;
-
-    if (hipMalloc(&B->d_info, sizeof(BeamInfo) * (size_t)nbeams) != hipSuccess ||
-        hipMalloc(&B->d_ptrs, sizeof(BeamPtrs) * (size_t)nbeams) != hipSuccess ||
-        hipMalloc(&B->d_tiles, sizeof(TileDesc) * tiles.size()) != hipSuccess ||
-        hipMalloc(&B->d_counters, sizeof(int) * (size_t)(ngroups + 2)) != hipSuccess ||
-        hipHostMalloc(&B->h_ptrs, sizeof(BeamPtrs) * (size_t)nbeams, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc(&B->h_err, sizeof(int), hipHostMallocDefault) != hipSuccess)
-        return pfb_internal_fail(PFB_E_NOMEM, "batched plan tables");
-    *B->h_err = 0;
-    if (hipMemcpy(B->d_info, B->info.data(), sizeof(BeamInfo) * (size_t)nbeams, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(B->d_tiles, tiles.data(), sizeof(TileDesc) * tiles.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemset(B->d_ptrs, 0, sizeof(BeamPtrs) * (size_t)nbeams) != hipSuccess)
-        return pfb_internal_fail(PFB_E_HIP, "batched plan upload");
-    B->last_ptrs.assign((size_t)nbeams, BeamPtrs{nullptr, nullptr, nullptr, nullptr});
 
     int dev = 0, cus = 256;
     hipDeviceProp_t prop;
@@ -415,25 +394,36 @@ static pfb_status build_batched(int32_t nbeams, const pfb_desc *beams, Batched *
         per_cu = 1;
     B->grid = std::min(cus * per_cu, B->ntiles);
 
+    if (hipMalloc(&B->d_info, sizeof(BeamInfo) * (size_t)nbeams) != hipSuccess ||
+        hipMalloc(&B->d_ptrs, sizeof(BeamPtrs) * (size_t)nbeams) != hipSuccess ||
+        hipMalloc(&B->d_tiles, sizeof(TileDesc) * tiles.size()) != hipSuccess ||
+        hipMalloc(&B->d_queue, sizeof(int)) != hipSuccess ||
+        hipMalloc(&B->d_slots, sizeof(float2) * (size_t)B->slot_elems * (size_t)B->grid) != hipSuccess ||
+        hipHostMalloc(&B->h_ptrs, sizeof(BeamPtrs) * (size_t)nbeams, hipHostMallocDefault) != hipSuccess)
+        return pfb_internal_fail(PFB_E_NOMEM, "batched plan tables and slots");
+    if (hipMemcpy(B->d_info, B->info.data(), sizeof(BeamInfo) * (size_t)nbeams, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(B->d_tiles, tiles.data(), sizeof(TileDesc) * tiles.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(B->d_ptrs, 0, sizeof(BeamPtrs) * (size_t)nbeams) != hipSuccess)
+        return pfb_internal_fail(PFB_E_HIP, "batched plan upload");
+    B->last_ptrs.assign((size_t)nbeams, BeamPtrs{nullptr, nullptr, nullptr, nullptr});
+
     BatchedArgs &a = B->args;
     a.beams = B->d_info;
     a.ptrs = B->d_ptrs;
     a.tiles = B->d_tiles;
-    a.queue = B->d_counters;
-    a.err = B->d_counters + 1;
-    a.deps = B->d_counters + 2;
+    a.queue = B->d_queue;
+    a.slots = B->d_slots;
+    a.slot_elems = B->slot_elems;
     a.ntiles = B->ntiles;
-    a.ngroups = ngroups;
-    a.spin_limit = 1LL << 26;
 
-    // graph: reset the counters, then the persistent kernel
+    // graph: reset the tile counter, then the persistent kernel
     if (hipGraphCreate(&B->graph, 0) != hipSuccess)
         return pfb_internal_fail(PFB_E_HIP, "hipGraphCreate");
     void *kargs[] = {&B->args};
     hipKernelNodeParams rp{};
     rp.func = reinterpret_cast<void *>(batched_reset_kernel);
-    rp.gridDim = dim3((unsigned)std::max(1, std::min(1024, (ngroups + 255) / 256)));
-    rp.blockDim = dim3(256);
+    rp.gridDim = dim3(1);
+    rp.blockDim = dim3(64);
     rp.sharedMemBytes = 0;
     rp.kernelParams = kargs;
     rp.extra = nullptr;
@@ -468,8 +458,8 @@ extern "C" pfb_status pfb_plan_create_batched(int32_t nbeams, const pfb_desc *be
             return pfb_internal_fail(PFB_E_INVALID, "batched beams are single streams (batch == 1)");
         if (beams[i].dtype != PFB_C64)
             return pfb_internal_fail(PFB_E_UNSUPPORTED, "batched beams take complex float32 input");
-        if (beams[i].taps > 32)
-            return pfb_internal_fail(PFB_E_UNSUPPORTED, "batched beams support up to 32 taps");
+        if (beams[i].taps > BT_MAX_TAPS)
+            return pfb_internal_fail(PFB_E_UNSUPPORTED, "batched beams support up to 64 taps");
     }
     Batched *B = new (std::nothrow) Batched();
     pfb_plan *p = pfb_internal_new_plan();
@@ -506,16 +496,10 @@ extern "C" pfb_status pfb_execute_batched(pfb_plan *p, const void *const *x, con
             return pfb_internal_fail(PFB_E_INVALID, "device pointers must be 16-byte aligned");
     }
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    // report a wait that overran its bound in an earlier call
-    if (B->launched && hipEventQuery(B->done) == hipSuccess && *B->h_err) {
-        *B->h_err = 0;
-        return pfb_internal_fail(PFB_E_HIP, "a batched dependency wait exceeded its bound in an earlier call");
-    }
     bool changed = false;
     for (int i = 0; i < B->nbeams; ++i) {
-        const BeamPtrs np{x[i], taps[i], reinterpret_cast<float2 *>(Y[i]), nullptr};
         const BeamPtrs &op = B->last_ptrs[(size_t)i];
-        if (np.x != op.x || np.h != op.h || np.Y != op.Y)
+        if (x[i] != op.x || taps[i] != op.h || Y[i] != (void *)op.Y)
             changed = true;
     }
     if (changed) {
@@ -532,8 +516,7 @@ extern "C" pfb_status pfb_execute_batched(pfb_plan *p, const void *const *x, con
     }
     if (hipGraphLaunch(B->exec, st) != hipSuccess)
         return pfb_internal_fail(PFB_E_HIP, "hipGraphLaunch");
-    if (hipMemcpyAsync(B->h_err, B->d_counters + 1, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipEventRecord(B->done, st) != hipSuccess)
+    if (hipEventRecord(B->done, st) != hipSuccess)
         return pfb_internal_fail(PFB_E_HIP, "batched completion record");
     B->launched = true;
     return PFB_OK;

@@ -33,6 +33,15 @@ template <int N, class F> __device__ __forceinline__ void sfor(F &&f)
 
 enum Dtype { DT_C64 = 0, DT_CI16 = 1, DT_CI8 = 2, DT_CF16 = 3 };
 
+// A pointer known to address global memory. Device functions that are not
+// inlined receive plain (generic) pointers, whose accesses the compiler must
+// issue as flat instructions; rebuilding the pointer in the global address
+// space lets it use global loads and stores again.
+template <typename T> __device__ __forceinline__ T *as_global(T *p)
+{
+    return (T *)(__attribute__((address_space(1))) T *)(uintptr_t)p;
+}
+
 template <int DT> struct SampleBytes;
 template <> struct SampleBytes<DT_C64> { static constexpr int value = 8; };
 template <> struct SampleBytes<DT_CI16> { static constexpr int value = 4; };

@@ -12,8 +12,9 @@ namespace pfb {
 constexpr int fir_prefetch(int tp) { return tp <= 16 ? 16 : 8; }
 
 // One wave's task: wave task gw of a FIR launch (channel chunk fastest, then
-// tile, then stream).
-template <int DT, int TP, int CPT, int D, bool REV>
+// tile, then stream). NT selects non-temporal stores (results that are not
+// read again soon) over plain ones (results read back by the same workgroup).
+template <int DT, int TP, int CPT, int D, bool REV, bool NT = true>
 __device__ __forceinline__ void fir_wave_task(const FirArgs &a, int64_t gw)
 {
     constexpr int U = TP > D ? TP : D; // outputs per unrolled step
@@ -79,8 +80,12 @@ __device__ __forceinline__ void fir_wave_task(const FirArgs &a, int64_t gw)
                     });
                     acc[k] = make_float2(ar, ai);
                 });
-                if (active)
-                    store_c64_nt<CPT>(yb + (int64_t)o * a.C, acc);
+                if (active) {
+                    if constexpr (NT)
+                        store_c64_nt<CPT>(yb + (int64_t)o * a.C, acc);
+                    else
+                        store_c64<CPT>(yb + (int64_t)o * a.C, acc);
+                }
             }
         });
     }

@@ -1,5 +1,8 @@
 // Tuning cache: a small text file, one entry per line,
-//   <arch> <dtype> <C> <T> <B> <S> path=<p> fir_cpt=<n> fir_sb=<n> fused_sb=<n> chunk_mib=<n>
+//   <arch> <dtype> <C> <T> <B> <S> path=<p> fir_cpt=<n> fir_sb=<n> fused_sb=<n> chunk_mib=<n> bwd_sb=<n>
+// for single plans, and
+//   <arch> batched <nbeams> <total samples> tile_kib=<n>
+// for batched plans.
 // Lines that do not parse are ignored, so a damaged cache degrades to the
 // built-in defaults rather than to an error.
 #include <hip/hip_runtime.h>
@@ -88,6 +91,52 @@ bool tune_lookup(const pfb_desc &d, TuneEntry *out)
     if (found)
         *out = best;
     return found;
+}
+
+static thread_local int g_batched_override = 0;
+
+void batched_tile_set_override(int kib) { g_batched_override = kib; }
+
+static long long batched_total_samples(int32_t nbeams, const pfb_desc *beams)
+{
+    long long tot = 0;
+    for (int i = 0; i < nbeams; ++i)
+        tot += (long long)beams[i].spectra * beams[i].channels;
+    return tot;
+}
+
+int batched_tile_kib(int32_t nbeams, const pfb_desc *beams)
+{
+    if (g_batched_override > 0)
+        return g_batched_override;
+    int kib = BATCHED_TILE_KIB_DEFAULT;
+    const char *path = std::getenv("PFB_TUNE_CACHE");
+    if (!path || !*path)
+        return kib;
+    FILE *f = std::fopen(path, "r");
+    if (!f)
+        return kib;
+    const std::string arch = device_arch_name();
+    const long long tot = batched_total_samples(nbeams, beams);
+    char line[512];
+    while (std::fgets(line, sizeof line, f)) {
+        char a[64], kw[16];
+        int nb = 0;
+        long long t = 0;
+        int used = 0;
+        if (std::sscanf(line, "%63s %15s %d %lld%n", a, kw, &nb, &t, &used) != 4)
+            continue;
+        if (arch != a || std::strcmp(kw, "batched") != 0 || nb != nbeams || t != tot)
+            continue;
+        char *rest = line + used;
+        for (char *tok = std::strtok(rest, " \t\r\n"); tok; tok = std::strtok(nullptr, " \t\r\n")) {
+            int v = 0;
+            if (parse_kv(tok, "tile_kib", &v) && v >= 16 && v <= (1 << 20))
+                kib = v; // the last matching line wins
+        }
+    }
+    std::fclose(f);
+    return kib;
 }
 
 } // namespace pfb
@@ -286,6 +335,101 @@ extern "C" pfb_status pfb_tune(const pfb_desc *desc, const char *cache_path)
     std::fprintf(f, "%s %d %d %d %d %lld path=%d fir_cpt=%d fir_sb=%d fused_sb=%d chunk_mib=%d bwd_sb=%d ms=%.5f\n",
                  device_arch_name().c_str(), d.dtype, d.channels, d.taps, d.batch, (long long)d.spectra, best.path,
                  best.fir_cpt, best.fir_sb, best.fused_sb, best.chunk_mib, best.bwd_sb, best_t);
+    std::fclose(f);
+    return PFB_OK;
+}
+
+extern "C" pfb_status pfb_tune_batched(int32_t nbeams, const pfb_desc *beams, const char *cache_path)
+{
+    if (nbeams < 1 || !beams)
+        return pfb_internal_fail(PFB_E_INVALID, "nbeams must be >= 1 and beams non-NULL");
+    if (!cache_path || !*cache_path)
+        return pfb_internal_fail(PFB_E_INVALID, "cache_path is empty");
+    for (int i = 0; i < nbeams; ++i) {
+        pfb_status st = pfb_internal_validate(&beams[i], true);
+        if (st != PFB_OK)
+            return st;
+    }
+    struct BeamBuf {
+        void *x = nullptr, *h = nullptr, *Y = nullptr;
+    };
+    std::vector<BeamBuf> bufs((size_t)nbeams);
+    auto release = [&]() {
+        for (BeamBuf &b : bufs)
+            for (void *p : {b.x, b.h, b.Y})
+                if (p)
+                    (void)hipFree(p);
+    };
+    for (int i = 0; i < nbeams; ++i) {
+        const pfb_desc &d = beams[i];
+        const size_t xb = (size_t)((d.spectra + d.taps - 1) * d.channels) * 8;
+        const size_t hb = (size_t)d.taps * d.channels * 4;
+        const size_t yb = (size_t)(d.spectra * d.channels) * 8;
+        BeamBuf &b = bufs[(size_t)i];
+        if (hipMalloc(&b.x, xb) != hipSuccess || hipMalloc(&b.h, hb) != hipSuccess ||
+            hipMalloc(&b.Y, yb) != hipSuccess || hipMemset(b.x, 0x11, xb) != hipSuccess ||
+            hipMemset(b.h, 0x11, hb) != hipSuccess) {
+            release();
+            return pfb_internal_fail(PFB_E_NOMEM, "tuner buffers");
+        }
+    }
+    std::vector<const void *> xs((size_t)nbeams);
+    std::vector<const float *> hs((size_t)nbeams);
+    std::vector<void *> Ys((size_t)nbeams);
+    for (int i = 0; i < nbeams; ++i) {
+        xs[(size_t)i] = bufs[(size_t)i].x;
+        hs[(size_t)i] = (const float *)bufs[(size_t)i].h;
+        Ys[(size_t)i] = bufs[(size_t)i].Y;
+    }
+    const bool verbose = std::getenv("PFB_TUNE_VERBOSE") != nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        release();
+        return pfb_internal_fail(PFB_E_HIP, "hipEventCreate");
+    }
+    double best_t = -1.0;
+    int best_kib = 0;
+    for (int kib : {256, 512, 1024, 2048, 4096}) {
+        batched_tile_set_override(kib);
+        pfb_plan *p = nullptr;
+        const pfb_status cs = pfb_plan_create_batched(nbeams, beams, &p);
+        batched_tile_set_override(0);
+        if (cs != PFB_OK)
+            continue;
+        auto call = [&]() { return pfb_execute_batched(p, xs.data(), hs.data(), Ys.data(), s); };
+        bool ok = call() == PFB_OK && call() == PFB_OK;
+        std::vector<float> ts;
+        for (int r = 0; r < 5 && ok; ++r) {
+            ok = hipEventRecord(e0, s) == hipSuccess && call() == PFB_OK && hipEventRecord(e1, s) == hipSuccess &&
+                 hipEventSynchronize(e1) == hipSuccess;
+            float ms = 0.0f;
+            if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+                ts.push_back(ms);
+        }
+        (void)hipStreamSynchronize(s);
+        pfb_plan_destroy(p);
+        if (!ok || ts.empty())
+            continue;
+        std::sort(ts.begin(), ts.end());
+        const double t = ts[ts.size() / 2];
+        if (verbose)
+            std::fprintf(stderr, "pfb_tune_batched: tile_kib=%d -> %.4f ms\n", kib, t);
+        if (best_t < 0 || t < best_t) {
+            best_t = t;
+            best_kib = kib;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    release();
+    if (best_t < 0)
+        return pfb_internal_fail(PFB_E_HIP, "no batched tuning candidate ran");
+    FILE *f = std::fopen(cache_path, "a");
+    if (!f)
+        return pfb_internal_fail(PFB_E_INVALID, "cannot open the tuning cache for writing");
+    std::fprintf(f, "%s batched %d %lld tile_kib=%d ms=%.5f\n", device_arch_name().c_str(), nbeams,
+                 pfb::batched_total_samples(nbeams, beams), best_kib, best_t);
     std::fclose(f);
     return PFB_OK;
 }

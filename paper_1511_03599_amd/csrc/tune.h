@@ -29,6 +29,15 @@ void tune_set_override(const TuneEntry *e);
 
 std::string device_arch_name();
 
+// Batched plans: the tile size (KiB of filtered spectra per tile) for this
+// beam table, from the thread's override, else the cache (lines
+//   <arch> batched <nbeams> <total samples> tile_kib=<k>
+// ), else the built-in default.
+int batched_tile_kib(int32_t nbeams, const pfb_desc *beams);
+void batched_tile_set_override(int kib); // 0 clears
+
+constexpr int BATCHED_TILE_KIB_DEFAULT = 1024;
+
 } // namespace pfb
 
 struct Batched;

@@ -49,8 +49,8 @@ class PlanInfo(ctypes.Structure):
 
 
 EXPORTED = ("pfb_plan_create", "pfb_execute", "pfb_backward", "pfb_plan_create_batched",
-            "pfb_execute_batched", "pfb_tune", "pfb_plan_get_info", "pfb_plan_destroy",
-            "pfb_status_str", "pfb_last_error")
+            "pfb_execute_batched", "pfb_tune", "pfb_tune_batched", "pfb_plan_get_info",
+            "pfb_plan_destroy", "pfb_status_str", "pfb_last_error")
 
 _lib = None
 
@@ -71,6 +71,7 @@ def lib():
     L.pfb_plan_create_batched.argtypes = [i32, ctypes.POINTER(Desc), ctypes.POINTER(vp)]
     L.pfb_execute_batched.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
     L.pfb_tune.argtypes = [ctypes.POINTER(Desc), ctypes.c_char_p]
+    L.pfb_tune_batched.argtypes = [i32, ctypes.POINTER(Desc), ctypes.c_char_p]
     L.pfb_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
     L.pfb_plan_destroy.argtypes = [vp]
     L.pfb_status_str.argtypes = [st]
@@ -78,7 +79,8 @@ def lib():
     L.pfb_last_error.argtypes = []
     L.pfb_last_error.restype = ctypes.c_char_p
     for f in ("pfb_plan_create", "pfb_execute", "pfb_backward", "pfb_plan_create_batched",
-              "pfb_execute_batched", "pfb_tune", "pfb_plan_get_info", "pfb_plan_destroy"):
+              "pfb_execute_batched", "pfb_tune", "pfb_tune_batched", "pfb_plan_get_info",
+              "pfb_plan_destroy"):
         getattr(L, f).restype = st
     _lib = L
     return L
@@ -205,11 +207,20 @@ class BatchedPlan:
     def __init__(self, beams):
         """beams: list of (C, T, S) tuples."""
         self.beams = [(int(C), int(T), int(S)) for (C, T, S) in beams]
-        n = len(self.beams)
-        arr = (Desc * n)(*[make_desc(C, T, S, 1, "c64", 0) for (C, T, S) in self.beams])
         h = ctypes.c_void_p()
-        check(lib().pfb_plan_create_batched(n, arr, ctypes.byref(h)))
+        check(lib().pfb_plan_create_batched(len(self.beams), self._descs(self.beams), ctypes.byref(h)))
         self._h = h
+
+    @staticmethod
+    def _descs(beams):
+        return (Desc * len(beams))(*[make_desc(C, T, S, 1, "c64", 0) for (C, T, S) in beams])
+
+    @staticmethod
+    def tune(beams, cache_path: str):
+        """Time the tile sizes for this beam table and append the fastest to
+        the tuning cache (read by plans created later via PFB_TUNE_CACHE)."""
+        beams = [(int(C), int(T), int(S)) for (C, T, S) in beams]
+        check(lib().pfb_tune_batched(len(beams), BatchedPlan._descs(beams), cache_path.encode()))
 
     def execute(self, xs, hs, Ys=None, stream=None):
         n = len(self.beams)

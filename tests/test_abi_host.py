@@ -29,7 +29,7 @@ def L():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for want in ("pfb_plan_create", "pfb_execute", "pfb_backward", "pfb_plan_create_batched",
-                 "pfb_execute_batched", "pfb_tune", "pfb_plan_destroy", "pfb_status_str",
+                 "pfb_execute_batched", "pfb_tune", "pfb_tune_batched", "pfb_plan_destroy", "pfb_status_str",
                  "pfb_last_error", "pfb_plan_get_info"):
         assert want in names
 

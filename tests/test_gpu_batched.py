@@ -11,7 +11,8 @@ from helpers import SPEC_TOL, c128, rel_l2, say, taps_to_device, to_device
 pytestmark = pytest.mark.gpu
 
 BEAMS = [(32, 4, 100), (128, 32, 1500), (8192, 8, 70), (1024, 16, 1031), (4096, 3, 90), (256, 1, 64),
-         (2048, 32, 33), (512, 17, 260), (64, 8, 5000), (8192, 32, 40)]
+         (2048, 32, 33), (512, 17, 260), (64, 8, 5000), (8192, 32, 40), (512, 64, 300), (8192, 40, 50),
+         (256, 12, 20000)]
 
 
 def make_beams(beams, seed):
@@ -77,6 +78,42 @@ def test_batched_rejects_bad_beams(dev):
     with pytest.raises(pfb.PFBError):
         pfb.BatchedPlan([(1000, 4, 10)])
     with pytest.raises(pfb.PFBError):
-        pfb.BatchedPlan([(1024, 33, 10)])
+        pfb.BatchedPlan([(1024, 65, 10)])
     with pytest.raises(pfb.PFBError):
         pfb.BatchedPlan([])
+
+
+def test_batched_tile_size_from_cache(dev, tmp_path, monkeypatch):
+    """A tuned tile size (here the smallest, so beams split into many tiles
+    with ragged last tiles) gives the same bits as the default one."""
+    import torch
+    from paper_1511_03599_amd import pfb
+    beams = [(8192, 8, 100), (1024, 16, 1031), (128, 4, 3000), (2048, 32, 77)]
+    xs, hs = make_beams(beams, 4000)
+    xd = [to_device(x, dev) for x in xs]
+    hd = [taps_to_device(h, dev) for h in hs]
+    ref = [Y.cpu().numpy() for Y in pfb.BatchedPlan(beams).execute(xd, hd)]
+    torch.cuda.synchronize()
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    total = sum(C * S for (C, T, S) in beams)
+    cache = tmp_path / "tune.txt"
+    cache.write_text(f"{arch} batched {len(beams)} {total} tile_kib=16\n")
+    monkeypatch.setenv("PFB_TUNE_CACHE", str(cache))
+    out = pfb.BatchedPlan(beams).execute(xd, hd)
+    torch.cuda.synchronize()
+    for i in range(len(beams)):
+        say(f"beam {i}: {beams[i]}")
+        assert np.array_equal(out[i].cpu().numpy(), ref[i]), i
+
+
+def test_batched_tuner_writes_cache(dev, tmp_path):
+    from paper_1511_03599_amd import pfb
+    beams = [(1024, 16, 2000), (256, 8, 4000)]
+    cache = tmp_path / "tune.txt"
+    pfb.BatchedPlan.tune(beams, str(cache))
+    lines = [l for l in cache.read_text().splitlines() if " batched " in l]
+    assert len(lines) == 1
+    f = lines[0].split()
+    assert f[1] == "batched" and int(f[2]) == 2 and int(f[3]) == 1024 * 2000 + 256 * 4000
+    kib = int(f[4].split("=")[1])
+    assert kib in (256, 512, 1024, 2048, 4096)
