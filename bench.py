@@ -282,7 +282,8 @@ def main():
     # dominant kernel of the step: the adjoint (one fused kernel plus the
     # small fixed-order tap-gradient reduction) or the fused forward kernel
     if t_bwd >= t_fwd:
-        name = "fused_bwd_kernel+gh_reduce_kernel" if info["backward_fused"] else "split_adjoint"
+        name = {"fused": "fused_bwd_kernel+gh_reduce_kernel", "fused_ws": "fused_bwd_ws_kernel+gh_reduce_kernel",
+                "split": "split_adjoint"}[info["backward_kind"]]
         t_dom, b_dom, tkey = t_bwd, bwd_bytes, f"pfb_backward_c{C}_t{T}_s{S}"
     else:
         name = "fused_fwd_kernel" if info["path"] == "fused" else "split_forward"
@@ -299,7 +300,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"pfb fwd+bwd, {B} stream x {S} spectra, C={C}, T={T}, complex64 noise",
                    "channels": C, "taps": T, "spectra": S, "streams": B, "path": info["path"],
-                   "backward_fused": info["backward_fused"]},
+                   "backward_fused": info["backward_fused"], "backward_kind": info["backward_kind"]},
         "hbm_gbs": round(step_gbs, 1), "hbm_frac": round(step_gbs / HBM_PEAK, 4),
         "fwd_ms": round(t_fwd, 5), "bwd_ms": round(t_bwd, 5),
         "fwd_gbs": round(fwd_bytes / t_fwd / 1e6, 1), "bwd_gbs": round(bwd_bytes / t_bwd / 1e6, 1),

@@ -108,8 +108,12 @@ typedef struct {
     int32_t padded_taps;   /* taps rounded up to the kernel's template size    */
     int64_t workspace_bytes;
     int64_t chunk_rows;    /* spectra per FIR/FFT chunk on the split path      */
-    int32_t backward_fused;/* 1 if pfb_backward runs the fused adjoint kernel  */
-    int32_t reserved;
+    int32_t backward_fused;/* pfb_backward runs: 0 the split adjoint (inverse
+                              FFT, reversed-tap FIR, tap-gradient pass),
+                              1 the fused adjoint kernel, 2 its
+                              wave-specialised form (same results)          */
+    int32_t fused_ws;      /* 1 if the fused forward runs its wave-specialised
+                              form (same results as the single-role kernel)  */
 } pfb_plan_info;
 
 /*

@@ -95,6 +95,7 @@ struct pfb_plan {
     int fir_cpt = 1;
     // fused tiling
     int fused_sb = 0;
+    bool fused_ws = false;       // wave-specialised fused kernel
     // split path chunking
     int64_t chunk_rows = 0;
     float2 *twiddle = nullptr;   // FFT twiddle table for C
@@ -106,6 +107,7 @@ struct pfb_plan {
     int64_t ws_gh_bytes = 0;
     int gh_sb = 256;
     bool bwd_fused = false;      // fused adjoint kernel
+    bool bwd_ws = false;         // ... its wave-specialised form
     int bwd_sb = 256;            // gx rows per fused adjoint tile
     int num_cus = 256;           // compute units of the plan's device
     // batched
@@ -291,7 +293,12 @@ static pfb_status plan_single(const pfb_desc *d, pfb_plan *p)
                !(tuned && te.path == PATH_SPLIT)) {
         p->path = PATH_FUSED;
         const int rb = fused_rows_per_chunk(p->tp, p->log2c);
-        p->fused_sb = choose_fused_sb(*d, rb);
+        if (tuned && te.fused_ws >= 0)
+            p->fused_ws = te.fused_ws != 0;
+        // the wave-specialised kernel pays a pipeline fill per tile: longer
+        // tiles, balanced over the CUs
+        p->fused_sb = p->fused_ws ? balanced_tile_rows(d->batch, d->spectra, rb, 128, p->num_cus)
+                                  : choose_fused_sb(*d, rb);
         if (tuned && te.fused_sb >= rb && te.fused_sb % rb == 0)
             p->fused_sb = te.fused_sb;
     } else {
@@ -303,26 +310,31 @@ static pfb_status plan_single(const pfb_desc *d, pfb_plan *p)
         st = make_twiddles(p->log2c, &p->twiddle);
         if (st != PFB_OK)
             return st;
-        // Split path workspace: the whole filtered-spectra array for the
-        // plain comparator; otherwise chunks of about 64 MiB, small enough to
-        // stay in the last-level cache between the FIR and FFT passes.
+        // Split path workspace (only the split path without a caller-given
+        // y uses it): by default the whole filtered-spectra array, so the
+        // FIR and the FFT each run as one launch (measured: chunks sized
+        // for the last-level cache lose more to per-launch ramps and tails
+        // than they gain); above 4 GiB, or with a tuned chunk size, the
+        // rows are processed in chunks.
         const int64_t row_bytes = (int64_t)d->channels * 8;
-        if (d->flags & PFB_PLAIN) {
-            p->chunk_rows = d->spectra;
-        } else {
-            int64_t target = (int64_t)64 << 20;
-            if (tuned && te.chunk_mib > 0)
-                target = (int64_t)te.chunk_mib << 20;
-            p->chunk_rows = target / (row_bytes * d->batch);
-            if (p->chunk_rows < 1)
-                p->chunk_rows = 1;
-            if (p->chunk_rows > d->spectra)
+        if (p->path == PATH_SPLIT) {
+            if (d->flags & PFB_PLAIN) {
                 p->chunk_rows = d->spectra;
+            } else {
+                int64_t target = (int64_t)4 << 30;
+                if (tuned && te.chunk_mib > 0)
+                    target = (int64_t)te.chunk_mib << 20;
+                p->chunk_rows = target / (row_bytes * d->batch);
+                if (p->chunk_rows < 1)
+                    p->chunk_rows = 1;
+                if (p->chunk_rows > d->spectra)
+                    p->chunk_rows = d->spectra;
+            }
+            p->ws_y_bytes = p->chunk_rows * row_bytes * d->batch;
+            st = dev_alloc(reinterpret_cast<void **>(&p->ws_y), p->ws_y_bytes, "split workspace");
+            if (st != PFB_OK)
+                return st;
         }
-        p->ws_y_bytes = p->chunk_rows * row_bytes * d->batch;
-        st = dev_alloc(reinterpret_cast<void **>(&p->ws_y), p->ws_y_bytes, "split workspace");
-        if (st != PFB_OK)
-            return st;
         if (d->dtype == PFB_C64) {
             p->bwd_fused = !(d->flags & (PFB_NO_FUSE | PFB_PLAIN)) && fused_bwd_supported(p->tp, p->log2c);
             // at least 128 gx rows per tile (the T-1 halo rows are transformed
@@ -330,6 +342,10 @@ static pfb_status plan_single(const pfb_desc *d, pfb_plan *p)
             p->bwd_sb = balanced_tile_rows(d->batch, d->spectra + d->taps - 1, 16, 128, p->num_cus);
             if (tuned && te.bwd_sb >= 16 && te.bwd_sb <= 65536)
                 p->bwd_sb = te.bwd_sb;
+            // measured: the wave-specialised adjoint is faster up to C = 512
+            p->bwd_ws = p->log2c <= 9;
+            if (tuned && te.bwd_ws >= 0)
+                p->bwd_ws = te.bwd_ws != 0;
             int64_t parts;
             if (p->bwd_fused) {
                 parts = (int64_t)d->batch * ceil_div(d->spectra + d->taps - 1, p->bwd_sb);
@@ -381,7 +397,8 @@ extern "C" pfb_status pfb_plan_get_info(const pfb_plan *p, pfb_plan_info *info)
     info->fir_cpt = p->fir_cpt;
     info->padded_taps = p->tp;
     info->workspace_bytes = p->ws_y_bytes + p->ws_gy_bytes + p->ws_gh_bytes;
-    info->backward_fused = p->bwd_fused ? 1 : 0;
+    info->backward_fused = p->bwd_fused ? (p->bwd_ws ? 2 : 1) : 0;
+    info->fused_ws = (p->path == PATH_FUSED && p->fused_ws) ? 1 : 0;
     info->chunk_rows = p->chunk_rows;
     return PFB_OK;
 }
@@ -465,7 +482,8 @@ extern "C" pfb_status pfb_execute(pfb_plan *p, const void *x, const float *taps,
         a.SB = p->fused_sb;
         a.n_tiles = (int)ceil_div(S, a.SB);
         a.S = S;
-        e = launch_fused(a, d.dtype, p->tp, p->log2c, st);
+        e = p->fused_ws ? launch_fused_ws(a, d.dtype, p->tp, p->log2c, st)
+                        : launch_fused(a, d.dtype, p->tp, p->log2c, st);
         return e == hipSuccess ? PFB_OK : hip_fail(e, "fused FIR+FFT launch");
     }
     if (y) {
@@ -528,7 +546,7 @@ extern "C" pfb_status pfb_backward(pfb_plan *p, const void *x, const float *taps
         a.SB = p->bwd_sb;
         a.n_tiles = (int)ceil_div(S + T - 1, a.SB);
         a.S = S;
-        e = launch_fused_bwd(a, p->tp, p->log2c, st);
+        e = p->bwd_ws ? launch_fused_bwd_ws(a, p->tp, p->log2c, st) : launch_fused_bwd(a, p->tp, p->log2c, st);
         if (e == hipSuccess && gh)
             e = launch_gh_reduce(p->ws_gh, gh, (int64_t)d.batch * a.n_tiles, T * C, st);
         return e == hipSuccess ? PFB_OK : hip_fail(e, "fused adjoint launch");

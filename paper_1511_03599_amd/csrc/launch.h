@@ -76,8 +76,10 @@ hipError_t launch_fir(const FirArgs &a, int dtype, int tp, int cpt, bool rev, hi
 hipError_t launch_gh(const GhArgs &a, int tp, float *gh, hipStream_t st);
 hipError_t launch_fft(const FftArgs &a, int log2c, bool inv, hipStream_t st);
 hipError_t launch_fused(const FusedArgs &a, int dtype, int tp, int log2c, hipStream_t st);
+hipError_t launch_fused_ws(const FusedArgs &a, int dtype, int tp, int log2c, hipStream_t st);
 bool fused_supported(int dtype, int tp, int log2c);
 hipError_t launch_fused_bwd(const BwdArgs &a, int tp, int log2c, hipStream_t st);
+hipError_t launch_fused_bwd_ws(const BwdArgs &a, int tp, int log2c, hipStream_t st);
 bool fused_bwd_supported(int tp, int log2c);
 hipError_t launch_gh_reduce(const float *part, float *gh, int64_t n_parts, int64_t tc, hipStream_t st);
 int fused_rows_per_chunk(int tp, int log2c);

@@ -1,5 +1,6 @@
 // Tuning cache: a small text file, one entry per line,
-//   <arch> <dtype> <C> <T> <B> <S> path=<p> fir_cpt=<n> fir_sb=<n> fused_sb=<n> chunk_mib=<n> bwd_sb=<n>
+//   <arch> <dtype> <C> <T> <B> <S> path=<p> fir_cpt=<n> fir_sb=<n> fused_sb=<n> fused_ws=<n> chunk_mib=<n>
+//   bwd_sb=<n> bwd_ws=<n>
 // for single plans, and
 //   <arch> batched <nbeams> <total samples> tile_kib=<n>
 // for batched plans.
@@ -81,8 +82,10 @@ bool tune_lookup(const pfb_desc &d, TuneEntry *out)
             parse_kv(tok, "fir_cpt", &e.fir_cpt);
             parse_kv(tok, "fir_sb", &e.fir_sb);
             parse_kv(tok, "fused_sb", &e.fused_sb);
+            parse_kv(tok, "fused_ws", &e.fused_ws);
             parse_kv(tok, "chunk_mib", &e.chunk_mib);
             parse_kv(tok, "bwd_sb", &e.bwd_sb);
+            parse_kv(tok, "bwd_ws", &e.bwd_ws);
         }
         best = e; // the last matching line wins
         found = true;
@@ -265,7 +268,7 @@ extern "C" pfb_status pfb_tune(const pfb_desc *desc, const char *cache_path)
                     e.fir_sb = sb;
                     cands.push_back(e);
                 } else {
-                    for (int mib : {32, 64, 128, 256}) {
+                    for (int mib : {0, 64, 256, 1024}) { // 0: one chunk
                         TuneEntry e;
                         e.path = 1;
                         e.fir_cpt = cpt;
@@ -283,12 +286,14 @@ extern "C" pfb_status pfb_tune(const pfb_desc *desc, const char *cache_path)
         const int l2 = ilog2_exact(d.channels);
         if (!(d.flags & (PFB_NO_FUSE | PFB_PLAIN)) && fused_supported(d.dtype, tp, l2)) {
             const int rb = tp > 16 ? tp : 16;
-            for (int m : {1, 2, 4, 8, 16, 32}) {
-                TuneEntry e;
-                e.path = 0;
-                e.fused_sb = rb * m;
-                cands.push_back(e);
-            }
+            for (int ws : {1, 0})
+                for (int m : {0, 1, 2, 4, 8, 16, 32}) {
+                    TuneEntry e;
+                    e.path = 0;
+                    e.fused_ws = ws;
+                    e.fused_sb = rb * m; // 0: the built-in choice
+                    cands.push_back(e);
+                }
         }
         add_split(1);
     }
@@ -298,8 +303,8 @@ extern "C" pfb_status pfb_tune(const pfb_desc *desc, const char *cache_path)
     for (const TuneEntry &e : cands) {
         const double t = time_candidate(d, e, buf, s, reps);
         if (verbose)
-            std::fprintf(stderr, "pfb_tune: path=%d fir_cpt=%d fir_sb=%d fused_sb=%d chunk_mib=%d -> %.4f ms\n",
-                         e.path, e.fir_cpt, e.fir_sb, e.fused_sb, e.chunk_mib, t);
+            std::fprintf(stderr, "pfb_tune: path=%d fir_cpt=%d fir_sb=%d fused_ws=%d fused_sb=%d chunk_mib=%d -> %.4f ms\n",
+                         e.path, e.fir_cpt, e.fir_sb, e.fused_ws, e.fused_sb, e.chunk_mib, t);
         if (t > 0 && (best_t < 0 || t < best_t)) {
             best_t = t;
             best = e;
@@ -314,27 +319,35 @@ extern "C" pfb_status pfb_tune(const pfb_desc *desc, const char *cache_path)
             hipMalloc(&buf.gh, (size_t)d.taps * d.channels * 4) == hipSuccess &&
             hipMemset(buf.y, 0x11, ybytes) == hipSuccess) {
             double best_b = -1.0;
-            int best_sb = 0;
-            for (int sb : {0, 128, 256, 512, 1024}) {
-                TuneEntry e = best;
-                e.bwd_sb = sb;
-                const double t = time_candidate(d, e, buf, s, reps, true);
-                if (verbose)
-                    std::fprintf(stderr, "pfb_tune: backward bwd_sb=%d -> %.4f ms\n", sb, t);
-                if (t > 0 && (best_b < 0 || t < best_b)) {
-                    best_b = t;
-                    best_sb = sb;
+            int best_sb = 0, best_ws = -1;
+            for (int ws : {1, 0}) {
+                for (int sb : {0, 128, 256, 512, 1024}) {
+                    TuneEntry e = best;
+                    e.bwd_sb = sb;
+                    e.bwd_ws = ws;
+                    const double t = time_candidate(d, e, buf, s, reps, true);
+                    if (verbose)
+                        std::fprintf(stderr, "pfb_tune: backward bwd_ws=%d bwd_sb=%d -> %.4f ms\n", ws, sb, t);
+                    if (t > 0 && (best_b < 0 || t < best_b)) {
+                        best_b = t;
+                        best_sb = sb;
+                        best_ws = ws;
+                    }
                 }
             }
             best.bwd_sb = best_sb;
+            best.bwd_ws = best_ws;
         }
     }
     FILE *f = std::fopen(cache_path, "a");
     if (!f)
         return pfb_internal_fail(PFB_E_INVALID, "cannot open the tuning cache for writing");
-    std::fprintf(f, "%s %d %d %d %d %lld path=%d fir_cpt=%d fir_sb=%d fused_sb=%d chunk_mib=%d bwd_sb=%d ms=%.5f\n",
+    std::fprintf(f,
+                 "%s %d %d %d %d %lld path=%d fir_cpt=%d fir_sb=%d fused_sb=%d fused_ws=%d chunk_mib=%d bwd_sb=%d "
+                 "bwd_ws=%d ms=%.5f\n",
                  device_arch_name().c_str(), d.dtype, d.channels, d.taps, d.batch, (long long)d.spectra, best.path,
-                 best.fir_cpt, best.fir_sb, best.fused_sb, best.chunk_mib, best.bwd_sb, best_t);
+                 best.fir_cpt, best.fir_sb, best.fused_sb, best.fused_ws, best.chunk_mib, best.bwd_sb, best.bwd_ws,
+                 best_t);
     std::fclose(f);
     return PFB_OK;
 }

@@ -14,8 +14,10 @@ struct TuneEntry {
     int fir_cpt = 0;     // FIR channels per thread
     int fir_sb = 0;      // FIR rows per tile
     int fused_sb = 0;    // fused rows per tile
+    int fused_ws = -1;   // fused forward: 1 wave-specialised, 0 single-role, -1 not set
     int chunk_mib = 0;   // split-path chunk size
     int bwd_sb = 0;      // fused adjoint rows per tile
+    int bwd_ws = -1;     // fused adjoint: 1 wave-specialised, 0 single-role, -1 not set
 };
 
 // Look the descriptor up in the cache file named by PFB_TUNE_CACHE. Returns

@@ -45,7 +45,7 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("fir_rows", ctypes.c_int32), ("fir_cpt", ctypes.c_int32),
                 ("padded_taps", ctypes.c_int32), ("workspace_bytes", ctypes.c_int64),
                 ("chunk_rows", ctypes.c_int64), ("backward_fused", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("fused_ws", ctypes.c_int32)]
 
 
 EXPORTED = ("pfb_plan_create", "pfb_execute", "pfb_backward", "pfb_plan_create_batched",
@@ -135,7 +135,9 @@ class Plan:
         check(lib().pfb_plan_get_info(self._h, ctypes.byref(i)))
         return {"path": PATH_NAMES.get(i.path, i.path), "fir_rows": i.fir_rows, "fir_cpt": i.fir_cpt,
                 "padded_taps": i.padded_taps, "workspace_bytes": i.workspace_bytes,
-                "chunk_rows": i.chunk_rows, "backward_fused": bool(i.backward_fused)}
+                "chunk_rows": i.chunk_rows, "backward_fused": bool(i.backward_fused),
+                "backward_kind": ("split", "fused", "fused_ws")[i.backward_fused],
+                "fused_ws": bool(i.fused_ws)}
 
     def _check_x(self, x):
         want = (self.B, self.rows, self.C)

@@ -30,6 +30,8 @@ def taps_to_device(h, dev):
 
 
 def c128(t) -> np.ndarray:
+    if isinstance(t, np.ndarray):
+        return t.astype(np.complex128)
     return t.detach().cpu().numpy().astype(np.complex128)
 
 

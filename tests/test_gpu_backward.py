@@ -17,20 +17,37 @@ def pfbmod():
     return pfb
 
 
+def adjoint_kind_cache(tmp_path, monkeypatch, C, T, S, B, ws):
+    """A tuning-cache entry that selects the wave-specialised (ws=1) or the
+    single-role (ws=0) fused adjoint."""
+    import torch
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    cache = tmp_path / f"tune{ws}.txt"
+    cache.write_text(f"{arch} 0 {C} {T} {B} {S} path=-1 bwd_ws={ws}\n")
+    monkeypatch.setenv("PFB_TUNE_CACHE", str(cache))
+
+
 @pytest.mark.parametrize("C,T,S,B", [(32, 4, 20, 2), (256, 8, 100, 2), (1024, 16, 80, 3), (4096, 5, 10, 1),
                                      (64, 64, 100, 1), (1024, 33, 70, 1), (512, 1, 40, 2), (128, 16, 600, 1),
                                      (1024, 16, 700, 2), (256, 3, 530, 1), (512, 13, 257, 2)])
-@pytest.mark.parametrize("mode", ["default", "split"])
-def test_backward_parity(dev, C, T, S, B, mode):
+@pytest.mark.parametrize("mode", ["default", "split", "single_role", "wave_specialised"])
+def test_backward_parity(dev, C, T, S, B, mode, tmp_path, monkeypatch):
     import torch
     pfb = pfbmod()
     say(f"backward C={C} T={T} S={S} B={B} {mode}")
     x = synth.quantise(synth.complex_gaussian((B, S + T - 1, C), 700 + C), "c64")
     h = synth.random_taps(C, T, 701)
     gY = synth.quantise(synth.complex_gaussian((B, S, C), 702), "c64")
+    if mode in ("single_role", "wave_specialised"):
+        adjoint_kind_cache(tmp_path, monkeypatch, C, T, S, B, int(mode == "wave_specialised"))
     plan = pfb.Plan(C, T, S, B, "c64", pfb.NO_FUSE if mode == "split" else 0)
-    if mode == "split":
-        assert not plan.info()["backward_fused"]
+    kind = plan.info()["backward_kind"]
+    if mode == "split" or not (256 <= C <= 1024 and T <= 16):
+        assert kind == "split"
+    elif mode == "default":
+        assert kind == ("fused_ws" if C <= 512 else "fused"), kind
+    else:
+        assert kind == ("fused" if mode == "single_role" else "fused_ws"), kind
     gx, gh = plan.backward(to_device(x, dev), taps_to_device(h, dev), to_device(gY, dev))
     torch.cuda.synchronize()
     gx_r, gh_r = oracle.pfb_adjoint(x, h, gY)
@@ -140,3 +157,25 @@ def test_full_size_differentiable_sampled(dev):
     lhs = (gx.real.double() * dx.real.double() + gx.imag.double() * dx.imag.double()).sum().item()
     rhs = (gY.real.double() * Ydx.real.double() + gY.imag.double() * Ydx.imag.double()).sum().item()
     assert abs(lhs - rhs) <= 1e-4 * abs(rhs)
+
+
+@pytest.mark.parametrize("C,T,S,B", [(1024, 16, 700, 2), (512, 8, 333, 1), (256, 4, 1000, 3), (1024, 5, 64, 1)])
+def test_wave_specialised_adjoint_equals_single_role(dev, C, T, S, B, tmp_path, monkeypatch):
+    """Both fused adjoint kernels do the same operations in the same order:
+    identical bits for gx and for the tap gradient."""
+    pfb = pfbmod()
+    say(f"ws vs single-role C={C} T={T} S={S} B={B}")
+    x = synth.quantise(synth.complex_gaussian((B, S + T - 1, C), 740), "c64")
+    h = synth.random_taps(C, T, 741)
+    gY = synth.quantise(synth.complex_gaussian((B, S, C), 742), "c64")
+    args = (to_device(x, dev), taps_to_device(h, dev), to_device(gY, dev))
+    adjoint_kind_cache(tmp_path, monkeypatch, C, T, S, B, 1)
+    p1 = pfb.Plan(C, T, S, B, "c64")
+    assert p1.info()["backward_kind"] == "fused_ws"
+    a = [t.cpu().numpy() for t in p1.backward(*args)]
+    adjoint_kind_cache(tmp_path, monkeypatch, C, T, S, B, 0)
+    p2 = pfb.Plan(C, T, S, B, "c64")
+    assert p2.info()["backward_kind"] == "fused"
+    b = [t.cpu().numpy() for t in p2.backward(*args)]
+    assert np.array_equal(a[0], b[0])
+    assert np.array_equal(a[1], b[1])

@@ -194,3 +194,56 @@ def test_full_size_sweep_sampled(dev, T):
         Yr, yr = oracle.pfb_forward(st.x[:, s:s + T], st.h, want_y=True)
         assert rel_l2(ys[i], yr[0, 0]) <= FIR_TOL, (s, plan_f.info())
         assert rel_l2(Ys[i], Yr[0, 0]) <= SPEC_TOL, (s, plan.info())
+
+
+@pytest.mark.parametrize("C,T,S,B,dtype", [(1024, 16, 700, 2, "c64"), (512, 8, 333, 1, "c64"), (256, 4, 1000, 3, "c64"),
+                                           (1024, 5, 67, 1, "ci8"), (256, 13, 257, 2, "ci16"), (512, 16, 90, 1, "cf16"),
+                                           (1024, 16, 3, 1, "c64")])
+def test_wave_specialised_forward_equals_single_role(dev, C, T, S, B, dtype, tmp_path, monkeypatch):
+    """Both fused forward kernels do the same operations in the same order:
+    identical bits, also with ragged last chunks and tiles."""
+    import torch
+    pfb = pfbmod()
+    say(f"fused ws vs single-role C={C} T={T} S={S} B={B} {dtype}")
+    x, h = make(C, T, S, B, dtype, 900 + C + T)
+    args = (to_device(x, dev), taps_to_device(h, dev))
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    dcode = {"c64": 0, "ci16": 1, "ci8": 2, "cf16": 3}[dtype]
+
+    def select(ws):
+        cache = tmp_path / f"tune{ws}.txt"
+        cache.write_text(f"{arch} {dcode} {C} {T} {B} {S} path=0 fused_ws={ws}\n")
+        monkeypatch.setenv("PFB_TUNE_CACHE", str(cache))
+    select(1)
+    p1 = pfb.Plan(C, T, S, B, dtype)
+    assert p1.info()["path"] == "fused" and p1.info()["fused_ws"]
+    a = p1.execute(*args).cpu().numpy()
+    select(0)
+    p2 = pfb.Plan(C, T, S, B, dtype)
+    assert p2.info()["path"] == "fused" and not p2.info()["fused_ws"]
+    b = p2.execute(*args).cpu().numpy()
+    assert np.array_equal(a, b)
+    ref = oracle.pfb_forward(x, h)
+    assert max(rel_l2_per_stream(c128(a), ref)) <= SPEC_TOL
+
+
+@pytest.mark.parametrize("C,T,S,B,mib", [(1024, 16, 700, 2, 1), (4096, 8, 90, 1, 1), (256, 32, 3000, 1, 2)])
+def test_chunked_split_equals_whole_split(dev, C, T, S, B, mib, tmp_path, monkeypatch):
+    """The split path processed in small chunks (tuned chunk size, ragged
+    last chunk) gives the bits of the one-chunk default."""
+    import torch
+    pfb = pfbmod()
+    say(f"chunked split C={C} T={T} S={S} B={B} chunk {mib} MiB")
+    x, h = make(C, T, S, B, "c64", 950 + C + T)
+    args = (to_device(x, dev), taps_to_device(h, dev))
+    p1 = pfb.Plan(C, T, S, B, "c64", pfb.NO_FUSE)
+    assert p1.info()["chunk_rows"] == S
+    a = p1.execute(*args).cpu().numpy()
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    cache = tmp_path / "tune.txt"
+    cache.write_text(f"{arch} 0 {C} {T} {B} {S} path=1 chunk_mib={mib}\n")
+    monkeypatch.setenv("PFB_TUNE_CACHE", str(cache))
+    p2 = pfb.Plan(C, T, S, B, "c64", pfb.NO_FUSE)
+    assert p2.info()["chunk_rows"] < S
+    b = p2.execute(*args).cpu().numpy()
+    assert np.array_equal(a, b)
