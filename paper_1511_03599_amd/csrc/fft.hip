@@ -12,10 +12,14 @@ template <int LOG2C> struct FftKernelShape {
     static constexpr int G = FL::G;
     static constexpr int NT = G > 256 ? G : 256; // threads per block
     static constexpr int F = NT / G;             // rows per block
+    // waves per SIMD the register allocation must allow (launch-bounds
+    // minimum): 4 lets two 512-thread blocks (C = 8192) share a CU, which
+    // at the unconstrained 169 VGPRs would run alone
+    static constexpr int MIN_WAVES = NT >= 512 ? 4 : 1;
 };
 
 template <int LOG2C, bool INV>
-__global__ __launch_bounds__(FftKernelShape<LOG2C>::NT) void fft_kernel(FftArgs a)
+__global__ __launch_bounds__(FftKernelShape<LOG2C>::NT, FftKernelShape<LOG2C>::MIN_WAVES) void fft_kernel(FftArgs a)
 {
     using K = FftKernelShape<LOG2C>;
     constexpr int G = K::G;

@@ -130,6 +130,16 @@ template <int LOG2C, int G> struct FftShape {
     static_assert(G * E == C, "shape");
 
     static __device__ __forceinline__ int pad(int idx) { return idx + (idx >> 4); }
+    // pad(a + i*STR) given pa = pad(a): for STR a multiple of 16 the padding
+    // grows by exactly i*STR/16, so the address is pa plus a constant and
+    // one base register serves every i
+    template <int STR> static __device__ __forceinline__ int pad_at(int a, int pa, int i)
+    {
+        if constexpr (STR % 16 == 0)
+            return pa + i * (STR + STR / 16);
+        else
+            return pad(a + i * STR);
+    }
     static constexpr int radix(int p) { return SCHED.radix(p); }
     static constexpr int stride(int p) { return SCHED.stride(p); }
     static constexpr int pass_offset(int p) { return SCHED.pass_offset(p); }
@@ -183,10 +193,13 @@ __device__ __forceinline__ void fft_passes(int lane, float2 *lds, const float2 *
 
         // gather (the first pass's inputs are already in v)
         if constexpr (P > 0) {
+            const int plane = S::pad(lane);
             sfor<NB>([&](auto q) PFB_INLINE {
                 const int j = lane + G * decltype(q)::value;
+                const int pj = S::template pad_at<G>(lane, plane, decltype(q)::value);
                 sfor<R>([&](auto i) PFB_INLINE {
-                    v[decltype(q)::value * R + decltype(i)::value] = lds[S::pad(j + decltype(i)::value * CR)];
+                    v[decltype(q)::value * R + decltype(i)::value] =
+                        lds[S::template pad_at<CR>(j, pj, decltype(i)::value)];
                 });
             });
         }
@@ -227,8 +240,9 @@ __device__ __forceinline__ void fft_passes(int lane, float2 *lds, const float2 *
                 const int j = lane + G * decltype(q)::value;
                 const int k = j & (L - 1);
                 const int o = (j - k) * R + k;
+                const int po = S::pad(o);
                 sfor<R>([&](auto i) PFB_INLINE {
-                    lds[S::pad(o + decltype(i)::value * L)] = v[decltype(q)::value * R + decltype(i)::value];
+                    lds[S::template pad_at<L>(o, po, decltype(i)::value)] = v[decltype(q)::value * R + decltype(i)::value];
                 });
             });
             group_sync<G>();
