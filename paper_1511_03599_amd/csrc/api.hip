@@ -342,8 +342,9 @@ static pfb_status plan_single(const pfb_desc *d, pfb_plan *p)
             p->bwd_sb = balanced_tile_rows(d->batch, d->spectra + d->taps - 1, 16, 128, p->num_cus);
             if (tuned && te.bwd_sb >= 16 && te.bwd_sb <= 65536)
                 p->bwd_sb = te.bwd_sb;
-            // measured: the wave-specialised adjoint is faster up to C = 512
-            p->bwd_ws = p->log2c <= 9;
+            // measured: the single-role adjoint is the faster default at
+            // every supported size (the tuner may still pick the other)
+            p->bwd_ws = false;
             if (tuned && te.bwd_ws >= 0)
                 p->bwd_ws = te.bwd_ws != 0;
             int64_t parts;

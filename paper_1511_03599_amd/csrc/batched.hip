@@ -155,7 +155,7 @@ __device__ __forceinline__ void batched_fft(const float2 *tw, const float2 *slot
                 lane, lds + gid * S::PADDED, tw, [&](int idx) { return in[idx]; },
                 [&](int idx, float2 v) { store_nt(o + idx, v); });
         }
-        __syncthreads(); // the LDS rows are reused by the next round
+        lds_barrier(); // the LDS rows are reused by the next round
     }
 }
 
@@ -179,15 +179,16 @@ __device__ __noinline__ int batched_run(const BatchedArgs &a, float2 *slot, floa
         const BeamInfo bm = as_global(a.beams)[td.beam];
         const BeamPtrs bp = as_global(a.ptrs)[td.beam];
         batched_fir<TP, CPT>(bm, as_global(bp.x), as_global(bp.h), slot, td.row0, td.nrows);
-        // the slot's rows, written by every wave, are read back by others
+        // the slot's rows, written to global memory by every wave, are read
+        // back by others: a full barrier (waits for the stores)
         __syncthreads();
         batched_fft<LOG2C>(as_global(bm.tw), slot, as_global(bp.Y) + td.row0 * bm.C, td.nrows, lds);
         // (batched_fft ends with a barrier: the slot and LDS are free again)
         if (threadIdx.x == 0)
             *s_tile = __hip_atomic_fetch_add(as_global(a.queue), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
+        lds_barrier();
         t = *s_tile;
-        __syncthreads();
+        lds_barrier();
         if (t >= a.ntiles || tiles[t].cls != bt_class(TP, LOG2C))
             return t;
     }
@@ -217,9 +218,9 @@ __global__ __launch_bounds__(BT_THREADS, 1) void batched_kernel(BatchedArgs a)
     float2 *slot = a.slots + (int64_t)blockIdx.x * a.slot_elems;
     if (threadIdx.x == 0)
         s_tile = __hip_atomic_fetch_add(a.queue, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
+    lds_barrier();
     int t = s_tile;
-    __syncthreads();
+    lds_barrier();
     while (t < a.ntiles) {
         const int cls = a.tiles[t].cls;
         const int log2c = 5 + cls % 9;

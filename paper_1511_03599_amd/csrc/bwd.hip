@@ -62,6 +62,12 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_bwd_kernel(BwdArgs a
     const int off = TP - a.T;
     const bool want_gx = a.gx != nullptr;
     const bool want_gh = a.part != nullptr;
+    const bool both = want_gx && want_gh;
+    enum { TAIL = 0, FULL = 1, LAST = 2 };
+    // the untested chunk form needs registers the 16-tap, two-channel
+    // window does not leave (it spills, and every reload waits for all
+    // memory operations): that variant tests each row
+    constexpr bool EXACT = !(TP >= 16 && CPT == 2);
 
     // window slot j of output p holds gy[p - (TP-1) + j], tap t = TP-1-j
     float hp[TP][CPT];
@@ -131,42 +137,65 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_bwd_kernel(BwdArgs a
             fft_passes<LOG2C, G, true, false>(lane, row, a.tw, cur,
                                               [&](int idx, float2 v) { row[S::pad(idx)] = v; });
         }
-        __syncthreads();
-        // 2. sample gradient and tap-gradient partials
-        sfor<RB>([&](auto jjc) {
-            constexpr int jj = decltype(jjc)::value;
-            const int i = base + jj; // gy row q0 + i
-            if (i < nq) {
-                sfor<CPT>([&](auto k) { w[jj % TP][k] = lds[jj * S::PADDED + S::pad(c0 + k)]; });
-                const int o = i - (TP - 1); // output row p0 + o
-                if (o >= 0) {
-                    // x[p0 + o] arrives from the prefetch ring
-                    // ring slot of x[p0 + o]: o mod D, a constant because base
-                    // is a multiple of RB (itself a multiple of D)
-                    constexpr int slot = ((jj - (TP - 1)) % D + D) % D;
-                    float2 xv[CPT];
-                    sfor<CPT>([&](auto k) { xv[k] = pf[slot][k]; });
-                    if (o + D < np)
-                        ldx(p0 + o + D, pf[slot]);
-                    float2 g[CPT];
-                    sfor<CPT>([&](auto k) {
-                        float gr = 0.0f, gi = 0.0f;
-                        sfor<TP>([&](auto jc) {
-                            constexpr int j = decltype(jc)::value;
-                            // slot of gy[p - (TP-1) + j]: (jj - (TP-1) + j) mod TP
-                            const float2 v = w[(jj + 1 + j) % TP][k];
-                            gr = __builtin_fmaf(hp[j][k], v.x, gr);
-                            gi = __builtin_fmaf(hp[j][k], v.y, gi);
-                            acc[j][k] = __builtin_fmaf(v.x, xv[k].x, __builtin_fmaf(v.y, xv[k].y, acc[j][k]));
-                        });
-                        g[k] = make_float2(gr, gi);
-                    });
-                    if (want_gx && o < np)
-                        store_c64_nt<CPT>(gxb + (p0 + o) * C + c0, g);
-                }
+        lds_barrier();
+        // 2. sample gradient and tap-gradient partials. In FULL chunks (every
+        // row an output of the tile, every x prefetch inside it, both
+        // gradients wanted) and in the LAST chunk of a tile (the same, with
+        // only its first RB-D rows prefetching) nothing is tested, so loads
+        // and stores are issued unconditionally and the compiler waits only
+        // for the x row a step uses; other chunks test each row.
+        auto grad_chunk = [&](auto kindc) PFB_INLINE {
+            constexpr int KIND = decltype(kindc)::value;
+            // row bases of this chunk (gx row and prefetched x row of jj = 0)
+            const float2 *xrow = nullptr;
+            float2 *gxrow = nullptr;
+            if constexpr (KIND != TAIL) {
+                xrow = wave_uniform(xb + (p0 + base - (TP - 1) + D) * C);
+                gxrow = wave_uniform(gxb + (p0 + base - (TP - 1)) * C);
             }
-        });
-        __syncthreads();
+            sfor<RB>([&](auto jjc) PFB_INLINE {
+                constexpr int jj = decltype(jjc)::value;
+                const int i = base + jj; // gy row q0 + i
+                if (KIND != TAIL || i < nq) {
+                    sfor<CPT>([&](auto k) PFB_INLINE { w[jj % TP][k] = lds[jj * S::PADDED + S::pad(c0 + k)]; });
+                    const int o = i - (TP - 1); // output row p0 + o
+                    if (KIND != TAIL || o >= 0) {
+                        // x[p0 + o] arrives from the prefetch ring; its slot,
+                        // o mod D, is a constant because base is a multiple of
+                        // RB (itself a multiple of D)
+                        constexpr int slot = ((jj - (TP - 1)) % D + D) % D;
+                        float2 xv[CPT];
+                        sfor<CPT>([&](auto k) PFB_INLINE { xv[k] = pf[slot][k]; });
+                        if constexpr (KIND == FULL || (KIND == LAST && jj < RB - D))
+                            Loader<DT_C64, CPT>::load(xrow, jj * C + c0, pf[slot]);
+                        else if (KIND == TAIL && o + D < np)
+                            ldx(p0 + o + D, pf[slot]);
+                        float2 g[CPT];
+                        sfor<CPT>([&](auto k) PFB_INLINE {
+                            float gr = 0.0f, gi = 0.0f;
+                            sfor<TP>([&](auto jc) PFB_INLINE {
+                                constexpr int j = decltype(jc)::value;
+                                // slot of gy[p - (TP-1) + j]: (jj - (TP-1) + j) mod TP
+                                const float2 v = w[(jj + 1 + j) % TP][k];
+                                gr = __builtin_fmaf(hp[j][k], v.x, gr);
+                                gi = __builtin_fmaf(hp[j][k], v.y, gi);
+                                acc[j][k] = __builtin_fmaf(v.x, xv[k].x, __builtin_fmaf(v.y, xv[k].y, acc[j][k]));
+                            });
+                            g[k] = make_float2(gr, gi);
+                        });
+                        if constexpr (KIND != TAIL)
+                            store_c64_nt<CPT>(gxrow + jj * C + c0, g);
+                        else if (want_gx && o < np)
+                            store_c64_nt<CPT>(gxb + (p0 + o) * C + c0, g);
+                    }
+                }
+            });
+        };
+        if (EXACT && both && base >= TP - 1 && base + RB <= nq && base + RB - TP + D < np)
+            grad_chunk(std::integral_constant<int, EXACT ? FULL : TAIL>{});
+        else
+            grad_chunk(std::integral_constant<int, TAIL>{});
+        lds_barrier();
     }
     if (want_gh) {
         float *pb = a.part + ((int64_t)b * a.n_tiles + tile) * (int64_t)a.T * C + c0;

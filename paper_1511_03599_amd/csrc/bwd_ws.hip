@@ -135,11 +135,11 @@ __global__ __launch_bounds__((WsShape<LOG2C, TP>::NT)) void fused_bwd_ws_kernel(
             };
             issue(0);
             finish(0, 0);
-            __syncthreads();
+            lds_barrier();
             for (int k = 0; k < nchunks; ++k) {
                 if (k + 1 < nchunks)
                     finish(k + 1, (k + 1) & 1);
-                __syncthreads();
+                lds_barrier();
             }
         } else {
             // Register budget too small to hold the next chunk's loads: each
@@ -172,11 +172,11 @@ __global__ __launch_bounds__((WsShape<LOG2C, TP>::NT)) void fused_bwd_ws_kernel(
                 }
             };
             produce(0, 0);
-            __syncthreads();
+            lds_barrier();
             for (int k = 0; k < nchunks; ++k) {
                 if (k + 1 < nchunks)
                     produce(k + 1, (k + 1) & 1);
-                __syncthreads();
+                lds_barrier();
             }
         }
         return;
@@ -199,7 +199,7 @@ __global__ __launch_bounds__((WsShape<LOG2C, TP>::NT)) void fused_bwd_ws_kernel(
     float2 w[TP][CPT];
     float2 *gxb = want_gx ? a.gx + (int64_t)b * rows * C : nullptr;
 
-    __syncthreads(); // chunk 0 staged
+    lds_barrier(); // chunk 0 staged
     for (int kb = 0; kb < nchunks; kb += W::UNR) {
         sfor<W::UNR>([&](auto jc) PFB_INLINE {
             constexpr int J = decltype(jc)::value;
@@ -238,7 +238,7 @@ __global__ __launch_bounds__((WsShape<LOG2C, TP>::NT)) void fused_bwd_ws_kernel(
                         }
                     }
                 });
-                __syncthreads();
+                lds_barrier();
             }
         });
     }

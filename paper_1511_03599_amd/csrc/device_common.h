@@ -33,6 +33,30 @@ template <int N, class F> __device__ __forceinline__ void sfor(F &&f)
 
 enum Dtype { DT_C64 = 0, DT_CI16 = 1, DT_CI8 = 2, DT_CF16 = 3 };
 
+// Workgroup barrier that orders LDS accesses only. __syncthreads() also
+// waits for every outstanding global load and store of the wave (its release
+// fence covers global memory), which would drain prefetched rows at each
+// barrier; where the waves exchange data through LDS alone, this barrier
+// lets global loads stay in flight across it.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// A wave-uniform pointer, moved into scalar registers. Row bases of an
+// unrolled block computed through this stay one scalar value per block:
+// otherwise loop strength reduction keeps one 64-bit vector induction
+// variable per unrolled row, which exhausts the registers.
+template <typename T> __device__ __forceinline__ T *wave_uniform(T *p)
+{
+    const uint64_t v = (uint64_t)(uintptr_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (T *)(uintptr_t)(((uint64_t)hi << 32) | lo);
+}
+
 // A pointer known to address global memory. Device functions that are not
 // inlined receive plain (generic) pointers, whose accesses the compiler must
 // issue as flat instructions; rebuilding the pointer in the global address
@@ -116,6 +140,22 @@ template <int DT, int V> __device__ __forceinline__ void zero_packed(Packed<DT, 
 #pragma unroll
     for (int k = 0; k < Packed<DT, V>::WORDS; ++k)
         p.w[k] = 0u;
+}
+
+// Load the fragment at sample index i when `valid`, zeros otherwise, without
+// a branch: the load is always issued (at index `safe`, known to be in
+// bounds, when not valid) and the result is masked. A load under a branch
+// would leave the number of memory operations in flight unknown to the
+// compiler, which then waits for all of them before the next use of any
+// prefetched value; issued unconditionally, the waits count exactly.
+template <int DT, int V>
+__device__ __forceinline__ void load_packed_masked(const void *base, int64_t i, int64_t safe, bool valid,
+                                                   Packed<DT, V> &p)
+{
+    load_packed<DT, V>(base, valid ? i : safe, p);
+#pragma unroll
+    for (int k = 0; k < Packed<DT, V>::WORDS; ++k)
+        p.w[k] = valid ? p.w[k] : 0u;
 }
 
 // Convert a packed fragment to float32 (exact for every storage type).

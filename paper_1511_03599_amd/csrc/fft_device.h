@@ -110,7 +110,7 @@ template <> struct Dft<16> {
 template <int G> __device__ __forceinline__ void group_sync()
 {
     if constexpr (G > 64) {
-        __syncthreads();
+        lds_barrier();
     } else {
         // One wave: LDS operations of a wave complete in order; only the
         // compiler has to be kept from moving accesses across this point.

@@ -42,34 +42,75 @@ __device__ __forceinline__ void fir_wave_task(const FirArgs &a, int64_t gw)
     });
 
     const char *xb = reinterpret_cast<const char *>(a.x) + (int64_t)b * a.in_bstride * SampleBytes<DT>::value;
-    auto ldp = [&](int64_t row, Packed<DT, CPT> &o) {
-        if (active && row >= 0 && row < a.in_rows)
-            load_packed<DT, CPT>(xb, row * a.C + c0, o);
-        else
-            zero_packed<DT, CPT>(o);
+    const int cs = active ? c0 : 0; // an in-bounds channel for every lane
+    // Loads are always issued, at a clamped (in-bounds) row, and never under
+    // a branch: the compiler then knows how many memory operations are in
+    // flight and waits only for the one a value comes from. Rows outside the
+    // stream read as zeros; that mask is applied when a row enters the
+    // window, not at its load, so no load is waited for early.
+    auto ldc = [&](int64_t row, Packed<DT, CPT> &o) {
+        const int64_t rs = row < 0 ? 0 : (row < a.in_rows ? row : a.in_rows - 1);
+        load_packed<DT, CPT>(xb, rs * a.C + cs, o);
+    };
+    auto enter_masked = [&](const Packed<DT, CPT> &p, float2 (&wv)[CPT], int64_t row) {
+        unpack<DT, CPT>(p, wv);
+        const bool ok = active && row >= 0 && row < a.in_rows;
+        sfor<CPT>([&](auto k) PFB_INLINE { wv[k] = ok ? wv[k] : make_float2(0.0f, 0.0f); });
     };
 
     float2 w[TP][CPT];
     Packed<DT, CPT> pf[D]; // prefetched rows, still packed
     sfor<TP - 1>([&](auto j) PFB_INLINE {
         Packed<DT, CPT> t;
-        ldp(row0 + j, t);
-        unpack<DT, CPT>(t, w[j]);
+        if constexpr (TP <= 16) {
+            ldc(row0 + j, t);
+            enter_masked(t, w[j], row0 + j);
+        } else {
+            const int64_t r = row0 + j;
+            if (active && r >= 0 && r < a.in_rows)
+                load_packed<DT, CPT>(xb, r * a.C + c0, t);
+            else
+                zero_packed<DT, CPT>(t);
+            unpack<DT, CPT>(t, w[j]);
+        }
     });
     sfor<D>([&](auto k) PFB_INLINE {
-        if (k < nout)
-            ldp(row0 + TP - 1 + k, pf[k]);
+        if constexpr (TP <= 16) {
+            ldc(row0 + TP - 1 + k, pf[k]); // masked when the row enters the window
+        } else {
+            const int64_t r = row0 + TP - 1 + k;
+            if (k < nout && active && r >= 0 && r < a.in_rows)
+                load_packed<DT, CPT>(xb, r * a.C + c0, pf[k]);
+            else
+                zero_packed<DT, CPT>(pf[k]);
+        }
     });
 
     float2 *yb = a.y + (int64_t)b * a.y_bstride + (s_begin - a.out_first) * a.C + c0;
-    for (int base = 0; base < nout; base += U) {
+    // One unrolled block of U outputs, of one of three kinds:
+    //   FULL  every output in the tile, every entering and prefetched row in
+    //         the stream, every lane on a channel: nothing is tested;
+    //   LAST  as FULL, but the block ends the tile, so only its first U-D
+    //         rows prefetch (a compile-time set): still nothing is tested;
+    //   TAIL  anything else (the last tile of a stream, the last partial
+    //         channel chunk, a ragged tile end): each row is tested and each
+    //         entering row masked.
+    enum { TAIL = 0, FULL = 1, LAST = 2 };
+    auto block = [&](int base, auto kindc) PFB_INLINE {
+        constexpr int KIND = decltype(kindc)::value;
         sfor<U>([&](auto jjc) PFB_INLINE {
             constexpr int jj = decltype(jjc)::value;
             const int o = base + jj;
-            if (o < nout) {
-                unpack<DT, CPT>(pf[jj % D], w[(jj + TP - 1) % TP]);
-                if (o + D < nout)
-                    ldp(row0 + o + D + TP - 1, pf[jj % D]);
+            const int64_t row_in = row0 + o + TP - 1; // row entering the window
+            if (KIND != TAIL || o < nout) {
+                if constexpr (KIND == TAIL) {
+                    enter_masked(pf[jj % D], w[(jj + TP - 1) % TP], row_in);
+                    ldc(row_in + D, pf[jj % D]);
+                } else {
+                    unpack<DT, CPT>(pf[jj % D], w[(jj + TP - 1) % TP]);
+                    if constexpr (KIND == FULL || jj < U - D)
+                        load_packed<DT, CPT>(xb, (row_in + D) * a.C + c0, pf[jj % D]);
+                }
                 float2 acc[CPT];
                 sfor<CPT>([&](auto k) PFB_INLINE {
                     float ar = 0.0f, ai = 0.0f;
@@ -80,7 +121,7 @@ __device__ __forceinline__ void fir_wave_task(const FirArgs &a, int64_t gw)
                     });
                     acc[k] = make_float2(ar, ai);
                 });
-                if (active) {
+                if (KIND != TAIL || active) {
                     if constexpr (NT)
                         store_c64_nt<CPT>(yb + (int64_t)o * a.C, acc);
                     else
@@ -88,6 +129,61 @@ __device__ __forceinline__ void fir_wave_task(const FirArgs &a, int64_t gw)
                 }
             }
         });
+    };
+    if constexpr (TP <= 16) {
+        int base = 0;
+        // wave-uniform: every lane on a channel, every entering row in the stream
+        const bool clean =
+            (cch + 1) * 64 * CPT <= a.C && row0 + TP - 1 >= 0 && row0 + nout + TP - 2 < a.in_rows;
+        if (clean) {
+            for (; base + U + D <= nout; base += U)
+                block(base, std::integral_constant<int, FULL>{});
+            if (base + U == nout) {
+                block(base, std::integral_constant<int, LAST>{});
+                base += U;
+            }
+        }
+        for (; base < nout; base += U)
+            block(base, std::integral_constant<int, TAIL>{});
+    } else {
+        // Windows of 32 taps and more: each row's 2T FMA per output hides
+        // the wait for its load, and the block kinds above (32-64 unrolled
+        // rows each) would cost a wave per SIMD in registers. One compact
+        // loop: rows outside the stream are not loaded but zeroed, and the
+        // prefetch stays inside the tile.
+        for (int base = 0; base < nout; base += U) {
+            sfor<U>([&](auto jjc) PFB_INLINE {
+                constexpr int jj = decltype(jjc)::value;
+                const int o = base + jj;
+                if (o < nout) {
+                    const int64_t row_in = row0 + o + TP - 1;
+                    unpack<DT, CPT>(pf[jj % D], w[(jj + TP - 1) % TP]);
+                    if (o + D < nout) {
+                        const int64_t r = row_in + D;
+                        if (active && r >= 0 && r < a.in_rows)
+                            load_packed<DT, CPT>(xb, r * a.C + c0, pf[jj % D]);
+                        else
+                            zero_packed<DT, CPT>(pf[jj % D]);
+                    }
+                    float2 acc[CPT];
+                    sfor<CPT>([&](auto k) PFB_INLINE {
+                        float ar = 0.0f, ai = 0.0f;
+                        sfor<TP>([&](auto jc) PFB_INLINE {
+                            constexpr int j = decltype(jc)::value;
+                            ar = __builtin_fmaf(hp[k][j], w[(jj + j) % TP][k].x, ar);
+                            ai = __builtin_fmaf(hp[k][j], w[(jj + j) % TP][k].y, ai);
+                        });
+                        acc[k] = make_float2(ar, ai);
+                    });
+                    if (active) {
+                        if constexpr (NT)
+                            store_c64_nt<CPT>(yb + (int64_t)o * a.C, acc);
+                        else
+                            store_c64<CPT>(yb + (int64_t)o * a.C, acc);
+                    }
+                }
+            });
+        }
     }
 }
 

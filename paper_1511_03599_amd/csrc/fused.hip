@@ -91,33 +91,52 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_fwd_kernel(FusedArgs
     const int lane = t % G;
     float2 *Yb = a.Y + ((int64_t)b * a.S + s_begin) * C;
 
-    for (int base = 0; base < nout; base += RB) {
-        // 1. FIR into the LDS row buffer
-#pragma unroll
-        for (int jj = 0; jj < RB; ++jj) {
+    // FIR rows of one chunk into the LDS row buffer. FULL chunks (every row
+    // and every prefetch inside the tile) and the LAST chunk of a tile (its
+    // rows inside the tile; only its first RB-D rows prefetch) issue their
+    // loads unconditionally, so the compiler counts the loads in flight and
+    // waits only for the row that enters the window; other chunks test each
+    // row. (Raw rows of a tile always lie inside the stream.)
+    enum { TAIL = 0, FULL = 1, LAST = 2 };
+    // the untested chunk form needs registers the 16-tap, two-channel
+    // window does not leave (it spills, and every reload waits for all
+    // memory operations): that variant tests each row
+    constexpr bool EXACT = !(TP >= 16 && CPT == 2);
+    auto fir_chunk = [&](int base, auto kindc) PFB_INLINE {
+        constexpr int KIND = decltype(kindc)::value;
+        // raw row prefetched by row jj = 0 of this chunk
+        const char *xrow = nullptr;
+        if constexpr (KIND != TAIL)
+            xrow = wave_uniform(xb + (row0 + base + D + TP - 1) * C * SampleBytes<DT>::value);
+        sfor<RB>([&](auto jjc) PFB_INLINE {
+            constexpr int jj = decltype(jjc)::value;
             const int o = base + jj;
-            if (o < nout) {
+            if (KIND != TAIL || o < nout) {
                 unpack<DT, CPT>(pf[jj % D], w[(jj + TP - 1) % TP]);
-                if (o + D < nout)
+                if constexpr (KIND == FULL || (KIND == LAST && jj < RB - D))
+                    load_packed<DT, CPT>(xrow, jj * C + c0, pf[jj % D]);
+                else if (KIND == TAIL && o + D < nout)
                     ldp(row0 + o + D + TP - 1, pf[jj % D]);
-#pragma unroll
-                for (int k = 0; k < CPT; ++k) {
+                sfor<CPT>([&](auto kc) PFB_INLINE {
+                    constexpr int k = decltype(kc)::value;
                     float ar = 0.0f, ai = 0.0f;
-#pragma unroll
-                    for (int j = 0; j < TP; ++j) {
+                    sfor<TP>([&](auto jc) PFB_INLINE {
+                        constexpr int j = decltype(jc)::value;
                         ar = __builtin_fmaf(hp[j][k], w[(jj + j) % TP][k].x, ar);
                         ai = __builtin_fmaf(hp[j][k], w[(jj + j) % TP][k].y, ai);
-                    }
+                    });
                     lds[jj * S::PADDED + S::pad(c0 + k)] = make_float2(ar, ai);
-                }
+                });
             }
-        }
-        __syncthreads();
-        // 2. FFT of the chunk's rows, straight to HBM
+        });
+    };
+    // the chunk's transforms, straight to HBM (ALL: every row in the tile)
+    auto fft_chunk = [&](int base, auto allc) PFB_INLINE {
+        constexpr bool ALL = decltype(allc)::value;
 #pragma unroll 1
         for (int round = 0; round < F::ROUNDS; ++round) {
             const int r = round * F::NG + gid;
-            const bool valid = base + r < nout;
+            const bool valid = ALL || base + r < nout;
             float2 *row = lds + r * S::PADDED;
             float2 *out = Yb + (int64_t)(base + r) * C;
             fft_run<LOG2C, G, false, true>(
@@ -127,7 +146,50 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_fwd_kernel(FusedArgs
                         store_nt(out + idx, v);
                 });
         }
-        __syncthreads();
+    };
+
+    if constexpr (EXACT) {
+        for (int base = 0; base < nout; base += RB) {
+            if (base + RB + D <= nout)
+                fir_chunk(base, std::integral_constant<int, FULL>{});
+            else if (base + RB == nout)
+                fir_chunk(base, std::integral_constant<int, LAST>{});
+            else
+                fir_chunk(base, std::integral_constant<int, TAIL>{});
+            lds_barrier();
+            if (base + RB <= nout)
+                fft_chunk(base, std::true_type{});
+            else
+                fft_chunk(base, std::false_type{});
+            lds_barrier();
+        }
+    } else {
+        for (int base = 0; base < nout; base += RB) {
+            // 1. FIR into the LDS row buffer
+#pragma unroll
+            for (int jj = 0; jj < RB; ++jj) {
+                const int o = base + jj;
+                if (o < nout) {
+                    unpack<DT, CPT>(pf[jj % D], w[(jj + TP - 1) % TP]);
+                    if (o + D < nout)
+                        ldp(row0 + o + D + TP - 1, pf[jj % D]);
+#pragma unroll
+                    for (int k = 0; k < CPT; ++k) {
+                        float ar = 0.0f, ai = 0.0f;
+#pragma unroll
+                        for (int j = 0; j < TP; ++j) {
+                            ar = __builtin_fmaf(hp[j][k], w[(jj + j) % TP][k].x, ar);
+                            ai = __builtin_fmaf(hp[j][k], w[(jj + j) % TP][k].y, ai);
+                        }
+                        lds[jj * S::PADDED + S::pad(c0 + k)] = make_float2(ar, ai);
+                    }
+                }
+            }
+            lds_barrier();
+            // 2. FFT of the chunk's rows, straight to HBM
+            fft_chunk(base, std::false_type{});
+            lds_barrier();
+        }
     }
 }
 

@@ -69,7 +69,7 @@ __global__ __launch_bounds__((FwsShape<LOG2C, TP, DT>::NT)) void fused_fwd_ws_ke
         const int r = (xl / 64) * F::TPW + (xl % 64) / G; // chunk row of this lane's group
         const int lane = xl % G;
         float2 *Yb = a.Y + ((int64_t)b * a.S + s_begin) * C;
-        __syncthreads(); // chunk 0 filtered
+        lds_barrier(); // chunk 0 filtered
         for (int k = 0; k < nchunks; ++k) {
             const int o = k * RB + r;
             const bool valid = o < nout;
@@ -81,7 +81,7 @@ __global__ __launch_bounds__((FwsShape<LOG2C, TP, DT>::NT)) void fused_fwd_ws_ke
                     if (valid)
                         store_nt(out + idx, v);
                 });
-            __syncthreads();
+            lds_barrier();
         }
         return;
     }
@@ -145,11 +145,11 @@ __global__ __launch_bounds__((FwsShape<LOG2C, TP, DT>::NT)) void fused_fwd_ws_ke
                         });
                     }
                 });
-                __syncthreads();
+                lds_barrier();
             }
         });
     }
-    __syncthreads(); // the FFT waves' last chunk
+    lds_barrier(); // the FFT waves' last chunk
 }
 
 template <int DT, int TP, int LOG2C> static hipError_t launch_fws_t(const FusedArgs &a, hipStream_t st)

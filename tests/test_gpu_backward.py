@@ -45,7 +45,7 @@ def test_backward_parity(dev, C, T, S, B, mode, tmp_path, monkeypatch):
     if mode == "split" or not (256 <= C <= 1024 and T <= 16):
         assert kind == "split"
     elif mode == "default":
-        assert kind == ("fused_ws" if C <= 512 else "fused"), kind
+        assert kind == "fused", kind
     else:
         assert kind == ("fused" if mode == "single_role" else "fused_ws"), kind
     gx, gh = plan.backward(to_device(x, dev), taps_to_device(h, dev), to_device(gY, dev))
