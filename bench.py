@@ -188,6 +188,44 @@ def extras_batched(dev, stream):
             "plain_64_launches_ms": round(tpl, 3), "speedup_vs_plain": round(tpl / tb, 3)}
 
 
+def extras_streaming(dev, stream):
+    """Real-time use: 8 consecutive chunks of 16384 new spectra (C=1024,
+    T=16, int16 samples) through a STREAMING plan. Compute-only: chunks
+    already in HBM. End-to-end: chunks from pinned host memory, frequency
+    spectra back to pinned host memory, copies overlapped with the filter
+    bank on three streams (StreamPipeline); this rate includes PCIe and is
+    never the headline value."""
+    import torch
+    from paper_1511_03599_amd import pfb, synth
+    C, T, S, k = 1024, 16, 16384, 8
+    plan = pfb.Plan(C, T, S, 1, "ci16", pfb.STREAMING)
+    h = torch.from_numpy(synth.windowed_sinc_taps(C, T)).to(dev)
+    g = torch.Generator().manual_seed(1511400)
+    chunks = [torch.randint(-2000, 2000, (1, S, C, 2), dtype=torch.int16, generator=g).pin_memory()
+              for _ in range(k)]
+    outs = [torch.empty((1, S, C), dtype=torch.complex64).pin_memory() for _ in range(k)]
+    buf = plan.stream_buffer(dev)
+    Y = torch.empty((1, S, C), dtype=torch.complex64, device=dev)
+    buf[:, T - 1:].copy_(chunks[0].to(dev))
+    for _ in range(3):
+        plan.execute_stream(buf, h, Y=Y)
+    t_comp = time_calls(lambda: plan.execute_stream(buf, h, Y=Y), 20, stream)
+    pipe = pfb.StreamPipeline(plan, h)
+    pipe.run(chunks[:2], outs[:2])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pipe.run(chunks, outs)
+    torch.cuda.synchronize()
+    t_e2e = (time.perf_counter() - t0) * 1e3 / k
+    samples = S * C
+    bytes_pcie = samples * (4 + 8)
+    return {"chunk_spectra": S, "chunks": k, "compute_ms_per_chunk": round(t_comp, 4),
+            "compute_msamples_s": round(samples / t_comp / 1e3, 1),
+            "end_to_end_ms_per_chunk": round(t_e2e, 4),
+            "end_to_end_msamples_s": round(samples / t_e2e / 1e3, 1),
+            "end_to_end_pcie_gbs": round(bytes_pcie / t_e2e / 1e6, 1)}
+
+
 def extras_differentiable(dev, stream):
     """32 streams x 8192 spectra, C=1024, T=16: forward, adjoint, and both."""
     import torch
@@ -323,6 +361,8 @@ def main():
         torch.cuda.empty_cache()
         log("bench: differentiable workload")
         extras["differentiable_b32_s8192_c1024_t16"] = extras_differentiable(dev, stream)
+        log("bench: streaming")
+        extras["streaming_c1024_t16_ci16"] = extras_streaming(dev, stream)
         out["extras"] = extras
 
     if args.copy_calibration:

@@ -77,9 +77,12 @@ typedef enum {
 enum {
     PFB_FIR_ONLY = 1u,      /* stop after the FIR: y is the output, Y unused  */
     PFB_NO_FUSE = 4u,       /* run FIR and FFT as separate passes             */
-    PFB_PLAIN = 8u          /* the untuned single-stream comparator: one FIR
+    PFB_PLAIN = 8u,         /* the untuned single-stream comparator: one FIR
                                launch over the whole stream into a workspace,
                                then one FFT launch; no fusion, no chunking   */
+    PFB_STREAMING = 16u     /* the plan carries the last T-1 raw spectra of
+                               each stream from one pfb_execute_stream call
+                               to the next (real-time use, Sec. 5)          */
 };
 
 /* Limits. */
@@ -136,6 +139,30 @@ pfb_status pfb_plan_create(const pfb_desc *desc, pfb_plan **out);
  */
 pfb_status pfb_execute(pfb_plan *plan, const void *x, const float *taps, void *y, void *Y,
                        void *stream);
+
+/*
+ * Streaming forward filter bank (plans created with PFB_STREAMING): the
+ * streams continue across calls, as if every call's new raw spectra were
+ * appended to one long input. Output s of a call is the filter bank of Alg. 1
+ * and Eq. (2) over the T raw spectra ending at its new raw spectrum s, the
+ * first T-1 of which may come from earlier calls (zeros before the first
+ * call or after pfb_stream_reset).
+ *   xbuf  device, [B][S+T-1][C] samples of the plan's dtype: per stream, the
+ *         last S rows hold the call's S new raw spectra and the first T-1
+ *         rows are headroom that the library overwrites with the carried
+ *         spectra (so the new data are never copied). The caller may reuse
+ *         the same buffer on every call.
+ *   taps, y, Y  as for pfb_execute (S filtered / frequency spectra per call).
+ * After the call the plan keeps the last T-1 rows of xbuf per stream.
+ * Calls on one plan must be ordered (same stream, or synchronised).
+ * Errors: PFB_E_STATE for a plan without PFB_STREAMING; otherwise those of
+ * pfb_execute.
+ */
+pfb_status pfb_execute_stream(pfb_plan *plan, void *xbuf, const float *taps, void *y, void *Y,
+                              void *stream);
+
+/* Zero the carried spectra of a streaming plan (on `stream`). */
+pfb_status pfb_stream_reset(pfb_plan *plan, void *stream);
 
 /*
  * Adjoint (backward) of the forward filter bank for a real loss, given

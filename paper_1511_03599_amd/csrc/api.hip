@@ -110,6 +110,9 @@ struct pfb_plan {
     bool bwd_ws = false;         // ... its wave-specialised form
     int bwd_sb = 256;            // gx rows per fused adjoint tile
     int num_cus = 256;           // compute units of the plan's device
+    // streaming: the last T-1 raw spectra of each stream, [B][T-1][C]
+    char *hist = nullptr;
+    int64_t hist_bytes = 0;
     // batched
     struct Batched *batched = nullptr;
 };
@@ -165,7 +168,7 @@ static pfb_status validate_desc(const pfb_desc *d, bool batched_beam)
         return fail(PFB_E_INVALID, "batch must be >= 1");
     if (bytes_per_sample(d->dtype) == 0)
         return fail(PFB_E_INVALID, "unknown dtype");
-    const uint32_t known = PFB_FIR_ONLY | PFB_NO_FUSE | PFB_PLAIN;
+    const uint32_t known = PFB_FIR_ONLY | PFB_NO_FUSE | PFB_PLAIN | PFB_STREAMING;
     if (!batched_beam && (d->flags & ~known))
         return fail(PFB_E_INVALID, "unknown flag bits");
     const bool fir_only = !batched_beam && (d->flags & PFB_FIR_ONLY);
@@ -195,9 +198,12 @@ static void free_plan_memory(pfb_plan *p)
         (void)hipFree(p->ws_gy);
     if (p->ws_gh)
         (void)hipFree(p->ws_gh);
+    if (p->hist)
+        (void)hipFree(p->hist);
     p->twiddle = nullptr;
     p->ws_y = p->ws_gy = nullptr;
     p->ws_gh = nullptr;
+    p->hist = nullptr;
 }
 
 static pfb_status dev_alloc(void **p, int64_t bytes, const char *what)
@@ -363,6 +369,14 @@ static pfb_status plan_single(const pfb_desc *d, pfb_plan *p)
                 return st;
         }
     }
+    if ((d->flags & PFB_STREAMING) && d->taps > 1) {
+        p->hist_bytes = (int64_t)d->batch * (d->taps - 1) * d->channels * bytes_per_sample(d->dtype);
+        pfb_status st2 = dev_alloc(reinterpret_cast<void **>(&p->hist), p->hist_bytes, "streaming history");
+        if (st2 != PFB_OK)
+            return st2;
+        if (hipMemset(p->hist, 0, (size_t)p->hist_bytes) != hipSuccess)
+            return fail(PFB_E_HIP, "hipMemset(streaming history)");
+    }
     return PFB_OK;
 }
 
@@ -447,7 +461,9 @@ static hipError_t run_fft(const pfb_plan *p, const float2 *in, float2 *out, int6
     return launch_fft(a, p->log2c, inv, st);
 }
 
-extern "C" pfb_status pfb_execute(pfb_plan *p, const void *x, const float *taps, void *y, void *Y, void *stream)
+// Argument checks of a forward call (before anything is launched).
+static pfb_status check_execute_args(const pfb_plan *p, const void *x, const float *taps, const void *y,
+                                     const void *Y)
 {
     if (!p)
         return fail(PFB_E_INVALID, "plan is NULL");
@@ -455,7 +471,6 @@ extern "C" pfb_status pfb_execute(pfb_plan *p, const void *x, const float *taps,
         return fail(PFB_E_STATE, "pfb_execute needs a single-problem plan");
     if (!x || !taps)
         return fail(PFB_E_INVALID, "x and taps must be non-NULL");
-    const pfb_desc &d = p->d;
     const bool fir_only = p->path == PATH_FIR_ONLY;
     if (fir_only && !y)
         return fail(PFB_E_INVALID, "a FIR-only plan needs y");
@@ -463,6 +478,16 @@ extern "C" pfb_status pfb_execute(pfb_plan *p, const void *x, const float *taps,
         return fail(PFB_E_INVALID, "Y must be non-NULL");
     if (!aligned16(x) || !aligned16(taps) || (y && !aligned16(y)) || (!fir_only && !aligned16(Y)))
         return fail(PFB_E_INVALID, "device pointers must be 16-byte aligned");
+    return PFB_OK;
+}
+
+extern "C" pfb_status pfb_execute(pfb_plan *p, const void *x, const float *taps, void *y, void *Y, void *stream)
+{
+    const pfb_status chk = check_execute_args(p, x, taps, y, Y);
+    if (chk != PFB_OK)
+        return chk;
+    const pfb_desc &d = p->d;
+    const bool fir_only = p->path == PATH_FIR_ONLY;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const int64_t C = d.channels, S = d.spectra;
     hipError_t e;
@@ -506,6 +531,54 @@ extern "C" pfb_status pfb_execute(pfb_plan *p, const void *x, const float *taps,
             return hip_fail(e, "FFT launch");
     }
     return PFB_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Streaming
+// ----------------------------------------------------------------------------
+
+extern "C" pfb_status pfb_execute_stream(pfb_plan *p, void *xbuf, const float *taps, void *y, void *Y,
+                                         void *stream)
+{
+    if (!p)
+        return fail(PFB_E_INVALID, "plan is NULL");
+    if (p->kind != KIND_SINGLE || !(p->d.flags & PFB_STREAMING))
+        return fail(PFB_E_STATE, "pfb_execute_stream needs a plan created with PFB_STREAMING");
+    const pfb_status chk = check_execute_args(p, xbuf, taps, y, Y);
+    if (chk != PFB_OK)
+        return chk;
+    const pfb_desc &d = p->d;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int64_t bs = bytes_per_sample(d.dtype);
+    const int64_t row_bytes = (int64_t)d.channels * bs;
+    const int64_t stream_bytes = (d.spectra + d.taps - 1) * row_bytes; // per stream in xbuf
+    const int64_t head = (int64_t)(d.taps - 1) * row_bytes;           // carried rows per stream
+    char *xb = static_cast<char *>(xbuf);
+    if (head > 0) {
+        // carried spectra into the headroom rows
+        hipError_t e = launch_copy_blocks(p->hist, head, xb, stream_bytes, head, d.batch, st);
+        if (e != hipSuccess)
+            return hip_fail(e, "streaming history copy-in");
+    }
+    pfb_status r = pfb_execute(p, xbuf, taps, y, Y, stream);
+    if (r != PFB_OK || head == 0)
+        return r;
+    // the last T-1 rows of every stream become the carried spectra
+    hipError_t e = launch_copy_blocks(xb + d.spectra * row_bytes, stream_bytes, p->hist, head, head, d.batch, st);
+    return e == hipSuccess ? PFB_OK : hip_fail(e, "streaming history copy-out");
+}
+
+extern "C" pfb_status pfb_stream_reset(pfb_plan *p, void *stream)
+{
+    if (!p)
+        return fail(PFB_E_INVALID, "plan is NULL");
+    if (p->kind != KIND_SINGLE || !(p->d.flags & PFB_STREAMING))
+        return fail(PFB_E_STATE, "pfb_stream_reset needs a plan created with PFB_STREAMING");
+    if (!p->hist)
+        return PFB_OK;
+    hipError_t e = launch_copy_blocks(nullptr, 0, p->hist, p->hist_bytes, p->hist_bytes, 1,
+                                      reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? PFB_OK : hip_fail(e, "streaming history reset");
 }
 
 // ----------------------------------------------------------------------------

@@ -77,6 +77,10 @@ hipError_t launch_gh(const GhArgs &a, int tp, float *gh, hipStream_t st);
 hipError_t launch_fft(const FftArgs &a, int log2c, bool inv, hipStream_t st);
 hipError_t launch_fused(const FusedArgs &a, int dtype, int tp, int log2c, hipStream_t st);
 hipError_t launch_fused_ws(const FusedArgs &a, int dtype, int tp, int log2c, hipStream_t st);
+// nblk blocks of `bytes` bytes from src + b*src_stride to dst + b*dst_stride
+// (src NULL: zeros).
+hipError_t launch_copy_blocks(const void *src, int64_t src_stride, void *dst, int64_t dst_stride, int64_t bytes,
+                              int64_t nblk, hipStream_t st);
 bool fused_supported(int dtype, int tp, int log2c);
 hipError_t launch_fused_bwd(const BwdArgs &a, int tp, int log2c, hipStream_t st);
 hipError_t launch_fused_bwd_ws(const BwdArgs &a, int tp, int log2c, hipStream_t st);

@@ -25,7 +25,7 @@ PFB_OK, PFB_E_INVALID, PFB_E_UNSUPPORTED, PFB_E_NOMEM, PFB_E_HIP, PFB_E_STATE = 
 # pfb_dtype
 DTYPE_CODES = {"c64": 0, "ci16": 1, "ci8": 2, "cf16": 3}
 # flags
-FIR_ONLY, NO_FUSE, PLAIN = 1, 4, 8
+FIR_ONLY, NO_FUSE, PLAIN, STREAMING = 1, 4, 8, 16
 PATH_NAMES = {0: "fused", 1: "split", 2: "fir_only"}
 MAX_TAPS = 64
 
@@ -48,9 +48,9 @@ class PlanInfo(ctypes.Structure):
                 ("fused_ws", ctypes.c_int32)]
 
 
-EXPORTED = ("pfb_plan_create", "pfb_execute", "pfb_backward", "pfb_plan_create_batched",
-            "pfb_execute_batched", "pfb_tune", "pfb_tune_batched", "pfb_plan_get_info",
-            "pfb_plan_destroy", "pfb_status_str", "pfb_last_error")
+EXPORTED = ("pfb_plan_create", "pfb_execute", "pfb_execute_stream", "pfb_stream_reset", "pfb_backward",
+            "pfb_plan_create_batched", "pfb_execute_batched", "pfb_tune", "pfb_tune_batched",
+            "pfb_plan_get_info", "pfb_plan_destroy", "pfb_status_str", "pfb_last_error")
 
 _lib = None
 
@@ -67,6 +67,8 @@ def lib():
     vp, i32, st = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int
     L.pfb_plan_create.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(vp)]
     L.pfb_execute.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.pfb_execute_stream.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.pfb_stream_reset.argtypes = [vp, vp]
     L.pfb_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.pfb_plan_create_batched.argtypes = [i32, ctypes.POINTER(Desc), ctypes.POINTER(vp)]
     L.pfb_execute_batched.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
@@ -78,9 +80,9 @@ def lib():
     L.pfb_status_str.restype = ctypes.c_char_p
     L.pfb_last_error.argtypes = []
     L.pfb_last_error.restype = ctypes.c_char_p
-    for f in ("pfb_plan_create", "pfb_execute", "pfb_backward", "pfb_plan_create_batched",
-              "pfb_execute_batched", "pfb_tune", "pfb_tune_batched", "pfb_plan_get_info",
-              "pfb_plan_destroy"):
+    for f in ("pfb_plan_create", "pfb_execute", "pfb_execute_stream", "pfb_stream_reset", "pfb_backward",
+              "pfb_plan_create_batched", "pfb_execute_batched", "pfb_tune", "pfb_tune_batched",
+              "pfb_plan_get_info", "pfb_plan_destroy"):
         getattr(L, f).restype = st
     _lib = L
     return L
@@ -166,6 +168,38 @@ class Plan:
             Y = torch.empty(out_shape, dtype=torch.complex64, device=x.device)
         check(lib().pfb_execute(self._h, _ptr(x), _ptr(h), _ptr(y), _ptr(Y), _stream(stream)))
         return Y
+
+    def stream_buffer(self, device=None) -> torch.Tensor:
+        """An input buffer for execute_stream: [B, S+T-1, C] of the plan's
+        dtype; write each call's new raw spectra into buf[:, T-1:]."""
+        shape = (self.B, self.rows, self.C)
+        if self.dtype == "c64":
+            return torch.zeros(shape, dtype=torch.complex64, device=device)
+        tdt = {"ci16": torch.int16, "ci8": torch.int8, "cf16": torch.float16}[self.dtype]
+        return torch.zeros(shape + (2,), dtype=tdt, device=device)
+
+    def execute_stream(self, xbuf, h, Y=None, y=None, stream=None):
+        """Streaming forward pass (plan created with STREAMING): xbuf holds the
+        call's S new raw spectra in rows T-1.. of each stream; rows 0..T-2 are
+        overwritten with the spectra carried from the previous call."""
+        if not self.flags & STREAMING:
+            raise PFBError(PFB_E_STATE, "execute_stream needs a plan created with STREAMING")
+        self._check_x(xbuf)
+        self._check_h(h)
+        out_shape = (self.B, self.S, self.C)
+        if self.flags & FIR_ONLY:
+            if y is None:
+                y = torch.empty(out_shape, dtype=torch.complex64, device=xbuf.device)
+            check(lib().pfb_execute_stream(self._h, _ptr(xbuf), _ptr(h), _ptr(y), None, _stream(stream)))
+            return y
+        if Y is None:
+            Y = torch.empty(out_shape, dtype=torch.complex64, device=xbuf.device)
+        check(lib().pfb_execute_stream(self._h, _ptr(xbuf), _ptr(h), _ptr(y), _ptr(Y), _stream(stream)))
+        return Y
+
+    def reset_stream(self, stream=None):
+        """Forget the carried spectra (the next call starts from zeros)."""
+        check(lib().pfb_stream_reset(self._h, _stream(stream)))
 
     def backward(self, x, h, gY, gx=None, gh=None, want_gx=True, want_gh=True, stream=None):
         """Adjoint pass for a real loss with frequency-spectra gradient gY.
@@ -255,6 +289,53 @@ class BatchedPlan:
             self.close()
         except Exception:
             pass
+
+
+class StreamPipeline:
+    """Real-time use of a STREAMING plan: chunks of raw spectra arrive in
+    (pinned) host memory and their frequency spectra go back to host memory.
+    Three streams overlap the host-to-device copy of chunk i+1, the filter
+    bank of chunk i and the device-to-host copy of chunk i-1; two device input
+    buffers and two output buffers alternate. The filter bank itself is the
+    plan's (pfb_execute_stream); this class only orders copies and launches."""
+
+    def __init__(self, plan: Plan, h: torch.Tensor, device=None):
+        if not plan.flags & STREAMING or plan.flags & FIR_ONLY:
+            raise PFBError(PFB_E_STATE, "StreamPipeline needs a STREAMING (not FIR-only) plan")
+        self.plan, self.h = plan, h
+        dev = device if device is not None else h.device
+        self.bufs = [plan.stream_buffer(dev), plan.stream_buffer(dev)]
+        self.outs = [torch.empty((plan.B, plan.S, plan.C), dtype=torch.complex64, device=dev) for _ in range(2)]
+        self.s_in, self.s_run, self.s_out = torch.cuda.Stream(dev), torch.cuda.Stream(dev), torch.cuda.Stream(dev)
+        self.ev_in = [torch.cuda.Event() for _ in range(2)]
+        self.ev_run = [torch.cuda.Event() for _ in range(2)]
+        self.ev_out = [torch.cuda.Event() for _ in range(2)]
+        self.used = [False, False]
+
+    def run(self, host_chunks, host_outs):
+        """host_chunks[i]: [B, S, C] (or [B, S, C, 2]) pinned host tensor of
+        chunk i's new raw spectra; host_outs[i]: pinned complex64 [B, S, C]
+        receiving its frequency spectra. Returns when all copies are done."""
+        T = self.plan.T
+        for i, (src, dst) in enumerate(zip(host_chunks, host_outs)):
+            k = i % 2
+            with torch.cuda.stream(self.s_in):
+                if self.used[k]:
+                    self.s_in.wait_event(self.ev_run[k])   # buffer k free again
+                self.bufs[k][:, T - 1:].copy_(src, non_blocking=True)
+                self.ev_in[k].record(self.s_in)
+            with torch.cuda.stream(self.s_run):
+                self.s_run.wait_event(self.ev_in[k])
+                if self.used[k]:
+                    self.s_run.wait_event(self.ev_out[k])  # output k copied out
+                self.plan.execute_stream(self.bufs[k], self.h, Y=self.outs[k], stream=self.s_run)
+                self.ev_run[k].record(self.s_run)
+            with torch.cuda.stream(self.s_out):
+                self.s_out.wait_event(self.ev_run[k])
+                dst.copy_(self.outs[k], non_blocking=True)
+                self.ev_out[k].record(self.s_out)
+            self.used[k] = True
+        self.s_out.synchronize()
 
 
 _plan_cache: dict = {}

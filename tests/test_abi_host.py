@@ -30,6 +30,7 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for want in ("pfb_plan_create", "pfb_execute", "pfb_backward", "pfb_plan_create_batched",
                  "pfb_execute_batched", "pfb_tune", "pfb_tune_batched", "pfb_plan_destroy", "pfb_status_str",
+                 "pfb_execute_stream", "pfb_stream_reset",
                  "pfb_last_error", "pfb_plan_get_info"):
         assert want in names
 
@@ -76,6 +77,8 @@ def test_null_arguments(L):
     assert L.pfb_plan_create(None, None) == 1
     assert L.pfb_execute(None, None, None, None, None, None) == 1
     assert L.pfb_backward(None, None, None, None, None, None, None) == 1
+    assert L.pfb_execute_stream(None, None, None, None, None, None) == 1
+    assert L.pfb_stream_reset(None, None) == 1
     assert L.pfb_plan_destroy(None) == 0
     assert L.pfb_status_str(0) == b"PFB_OK"
     assert b"INVALID" in L.pfb_status_str(1)
