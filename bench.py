@@ -226,6 +226,28 @@ def extras_streaming(dev, stream):
             "end_to_end_pcie_gbs": round(bytes_pcie / t_e2e / 1e6, 1)}
 
 
+def extras_mixed_radix(dev, stream):
+    """Channel counts that are not powers of two (mixed-radix transform on the
+    split path) beside their power-of-two neighbours: T=16, 2^27 samples."""
+    import torch
+    from paper_1511_03599_amd import metrics, pfb, synth
+    out = {}
+    for C in (2048, 3072, 4096, 6144):
+        T, S = 16, (1 << 27) // C
+        x = synth.device_noise((1, S + T - 1, C), 1511500 + C, dev)
+        h = torch.from_numpy(synth.windowed_sinc_taps(C, T)).to(dev)
+        Y = torch.empty((1, S, C), dtype=torch.complex64, device=dev)
+        p = pfb.Plan(C, T, S, 1, "c64")
+        for _ in range(2):
+            p.execute(x, h, Y=Y)
+        t = time_calls(lambda: p.execute(x, h, Y=Y), 10, stream)
+        out[str(C)] = {"pfb_ms": round(t, 4), "pfb_msamples_s": round(S * C / t / 1e3, 1),
+                       "path": p.info()["path"],
+                       "fused_bytes_gbs": round(metrics.pfb_fused_bytes(1, S, C, T) / t / 1e6, 1)}
+        del p, x, Y
+    return out
+
+
 def extras_differentiable(dev, stream):
     """32 streams x 8192 spectra, C=1024, T=16: forward, adjoint, and both."""
     import torch
@@ -361,6 +383,9 @@ def main():
         torch.cuda.empty_cache()
         log("bench: differentiable workload")
         extras["differentiable_b32_s8192_c1024_t16"] = extras_differentiable(dev, stream)
+        log("bench: mixed-radix channel counts")
+        extras["mixed_radix_t16"] = extras_mixed_radix(dev, stream)
+        torch.cuda.empty_cache()
         log("bench: streaming")
         extras["streaming_c1024_t16_ci16"] = extras_streaming(dev, stream)
         out["extras"] = extras

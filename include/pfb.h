@@ -93,7 +93,10 @@ enum {
 /* One filter-bank problem. `spectra` counts filtered (output) spectra; the
  * input has spectra + taps - 1 raw spectra per stream. */
 typedef struct {
-    int32_t channels;  /* C >= 1; a power of two in [32, 8192] unless FIR_ONLY */
+    int32_t channels;  /* C >= 1; unless FIR_ONLY, C in [32, 8192] and of the
+                          form 2^a 3^b 5^c 7^d (powers of two take the fused
+                          paths, other sizes the split path with a
+                          mixed-radix transform)                            */
     int32_t taps;      /* T in [1, PFB_MAX_TAPS]                               */
     int64_t spectra;   /* S >= 1                                               */
     int32_t batch;     /* B >= 1 independent streams                           */

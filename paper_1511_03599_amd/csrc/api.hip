@@ -99,6 +99,8 @@ struct pfb_plan {
     // split path chunking
     int64_t chunk_rows = 0;
     float2 *twiddle = nullptr;   // FFT twiddle table for C
+    bool mixed = false;          // C not a power of two: mixed-radix transform
+    GfftSched gf{};
     float2 *ws_y = nullptr;      // filtered spectra workspace (split path)
     int64_t ws_y_bytes = 0;
     float2 *ws_gy = nullptr;     // backward: inverse-transformed gradient
@@ -120,6 +122,27 @@ struct pfb_plan {
 // ----------------------------------------------------------------------------
 // Twiddles
 // ----------------------------------------------------------------------------
+
+// exp(-2 pi i m / C) for m < C (mixed-radix transforms), FP64 rounded once.
+static pfb_status make_twiddles_mixed(int C, float2 **out)
+{
+    std::vector<float2> host((size_t)C);
+    for (int m = 0; m < C; ++m) {
+        const double a = -2.0 * M_PI * (double)m / (double)C;
+        host[(size_t)m] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, sizeof(float2) * (size_t)C);
+    if (e != hipSuccess)
+        return fail(PFB_E_NOMEM, std::string("hipMalloc(twiddles): ") + hipGetErrorString(e));
+    e = hipMemcpy(p, host.data(), sizeof(float2) * (size_t)C, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(p);
+        return hip_fail(e, "hipMemcpy(twiddles)");
+    }
+    *out = reinterpret_cast<float2 *>(p);
+    return PFB_OK;
+}
 
 static pfb_status make_twiddles(int log2c, float2 **out)
 {
@@ -174,8 +197,13 @@ static pfb_status validate_desc(const pfb_desc *d, bool batched_beam)
     const bool fir_only = !batched_beam && (d->flags & PFB_FIR_ONLY);
     if (!fir_only) {
         const int l2 = ilog2_exact(d->channels);
-        if (l2 < 0 || d->channels < PFB_MIN_FFT_CHANNELS || d->channels > PFB_MAX_FFT_CHANNELS)
-            return fail(PFB_E_UNSUPPORTED, "the FFT needs channels a power of two in [32, 8192]");
+        GfftSched gs;
+        if (d->channels < PFB_MIN_FFT_CHANNELS || d->channels > PFB_MAX_FFT_CHANNELS)
+            return fail(PFB_E_UNSUPPORTED, "the FFT needs channels in [32, 8192]");
+        if (batched_beam && l2 < 0)
+            return fail(PFB_E_UNSUPPORTED, "batched beams need channels a power of two");
+        if (l2 < 0 && !gfft_schedule(d->channels, &gs))
+            return fail(PFB_E_UNSUPPORTED, "the FFT needs channels of the form 2^a 3^b 5^c 7^d");
     }
     // every element count must fit comfortably in int64
     int64_t rows = d->spectra + d->taps - 1, t = 0, u = 0;
@@ -313,7 +341,14 @@ static pfb_status plan_single(const pfb_desc *d, pfb_plan *p)
 
     pfb_status st;
     if (!fir_only) {
-        st = make_twiddles(p->log2c, &p->twiddle);
+        if (p->log2c < 0) {
+            p->mixed = true;
+            if (!gfft_schedule(d->channels, &p->gf))
+                return fail(PFB_E_UNSUPPORTED, "no radix schedule for this channel count");
+            st = make_twiddles_mixed(d->channels, &p->twiddle);
+        } else {
+            st = make_twiddles(p->log2c, &p->twiddle);
+        }
         if (st != PFB_OK)
             return st;
         // Split path workspace (only the split path without a caller-given
@@ -458,6 +493,8 @@ static hipError_t run_fft(const pfb_plan *p, const float2 *in, float2 *out, int6
     a.rows_per_group = rows_per_group;
     a.in_gstride = in_gstride;
     a.out_gstride = out_gstride;
+    if (p->mixed)
+        return launch_gfft(a, p->gf, inv, st);
     return launch_fft(a, p->log2c, inv, st);
 }
 

@@ -75,6 +75,18 @@ struct BwdArgs {
 hipError_t launch_fir(const FirArgs &a, int dtype, int tp, int cpt, bool rev, hipStream_t st);
 hipError_t launch_gh(const GhArgs &a, int tp, float *gh, hipStream_t st);
 hipError_t launch_fft(const FftArgs &a, int log2c, bool inv, hipStream_t st);
+
+// Mixed-radix transform for C = 2^a 3^b 5^c 7^d (not a power of two).
+constexpr int GF_MAX_PASS = 16;
+struct GfftSched {
+    int C;
+    int npass;
+    int group;           // lanes per row: 64 or 256
+    int rows_per_block;
+    int radix[GF_MAX_PASS];
+};
+bool gfft_schedule(int C, GfftSched *s);
+hipError_t launch_gfft(const FftArgs &a, const GfftSched &s, bool inv, hipStream_t st);
 hipError_t launch_fused(const FusedArgs &a, int dtype, int tp, int log2c, hipStream_t st);
 hipError_t launch_fused_ws(const FusedArgs &a, int dtype, int tp, int log2c, hipStream_t st);
 // nblk blocks of `bytes` bytes from src + b*src_stride to dst + b*dst_stride

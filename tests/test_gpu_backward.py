@@ -29,7 +29,8 @@ def adjoint_kind_cache(tmp_path, monkeypatch, C, T, S, B, ws):
 
 @pytest.mark.parametrize("C,T,S,B", [(32, 4, 20, 2), (256, 8, 100, 2), (1024, 16, 80, 3), (4096, 5, 10, 1),
                                      (64, 64, 100, 1), (1024, 33, 70, 1), (512, 1, 40, 2), (128, 16, 600, 1),
-                                     (1024, 16, 700, 2), (256, 3, 530, 1), (512, 13, 257, 2)])
+                                     (1024, 16, 700, 2), (256, 3, 530, 1), (512, 13, 257, 2),
+                                     (384, 8, 50, 2), (3072, 4, 12, 1), (105, 16, 40, 1)])
 @pytest.mark.parametrize("mode", ["default", "split", "single_role", "wave_specialised"])
 def test_backward_parity(dev, C, T, S, B, mode, tmp_path, monkeypatch):
     import torch
@@ -42,7 +43,7 @@ def test_backward_parity(dev, C, T, S, B, mode, tmp_path, monkeypatch):
         adjoint_kind_cache(tmp_path, monkeypatch, C, T, S, B, int(mode == "wave_specialised"))
     plan = pfb.Plan(C, T, S, B, "c64", pfb.NO_FUSE if mode == "split" else 0)
     kind = plan.info()["backward_kind"]
-    if mode == "split" or not (256 <= C <= 1024 and T <= 16):
+    if mode == "split" or not (C in (256, 512, 1024) and T <= 16):
         assert kind == "split"
     elif mode == "default":
         assert kind == "fused", kind

@@ -247,3 +247,43 @@ def test_chunked_split_equals_whole_split(dev, C, T, S, B, mib, tmp_path, monkey
     assert p2.info()["chunk_rows"] < S
     b = p2.execute(*args).cpu().numpy()
     assert np.array_equal(a, b)
+
+
+MIXED = [(96, 8), (105, 4), (384, 16), (1000, 5), (3072, 16), (2401, 3), (6144, 8), (3125, 2), (448, 32)]
+
+
+@pytest.mark.parametrize("C,T", MIXED)
+@pytest.mark.parametrize("dtype", ["c64", "ci8"])
+def test_forward_parity_mixed_radix(dev, C, T, dtype):
+    """Channel counts that are not powers of two (mixed-radix transform,
+    split path) against the oracle's O(C^2) DFT."""
+    pfb = pfbmod()
+    S, B = rows_for(C) + 1, 2
+    say(f"mixed-radix forward C={C} T={T} S={S} {dtype}")
+    x, h = make(C, T, S, B, dtype, 1400 + C + T)
+    plan = pfb.Plan(C, T, S, B, dtype)
+    assert plan.info()["path"] == "split"
+    Y = plan.execute(to_device(x, dev), taps_to_device(h, dev))
+    ref = oracle.pfb_forward(x, h)
+    errs = rel_l2_per_stream(c128(Y), ref)
+    assert max(errs) <= SPEC_TOL, errs
+
+
+def test_mixed_radix_tone_bin(dev):
+    """A pure tone at bin k of C=3072 lands in bin k only (to FP32 rounding)."""
+    pfb = pfbmod()
+    C, T, S, k = 3072, 1, 4, 1234
+    x = synth.quantise(synth.centre_tone(S, C, k)[None], "c64")
+    h = np.ones((1, C), dtype=np.float32)
+    Y = pfb.Plan(C, T, S, 1, "c64").execute(to_device(x, dev), taps_to_device(h, dev)).cpu().numpy()[0]
+    mag = np.abs(Y)
+    assert np.all(np.argmax(mag, axis=-1) == k)
+    assert np.max(np.delete(mag, k, axis=-1)) <= 1e-3 * np.max(mag)
+
+
+def test_non_smooth_channels_rejected(dev):
+    pfb = pfbmod()
+    with pytest.raises(pfb.PFBError):
+        pfb.Plan(8190, 4, 10)
+    with pytest.raises(pfb.PFBError):
+        pfb.BatchedPlan([(96, 4, 10)])

@@ -86,7 +86,7 @@ def test_fir_shift_equivariance_exact():
 
 # --- DFT (Eq. (2)) ---------------------------------------------------------------
 
-@pytest.mark.parametrize("C", [1, 2, 3, 8, 12, 64])
+@pytest.mark.parametrize("C", [1, 2, 3, 8, 12, 64, 96, 105, 3072])
 def test_single_tap_unit_filter_is_library_fft(C):
     """With T=1 and h=1 the filter bank is the DFT of each raw spectrum."""
     x = synth.complex_gaussian((2, 5, C), 41 + C)
