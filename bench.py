@@ -105,7 +105,7 @@ def extras_sweep(dev, stream, C, S):
     from paper_1511_03599_amd import metrics, pfb, synth
     out = {}
     Y = torch.empty((1, S, C), dtype=torch.complex64, device=dev)
-    for T in (4, 8, 16, 32, 64):
+    for T in (4, 8, 16, 32, 64, 128, 192):
         st = synth.noise_stream(1, C, T, S, synth.seed_for(2, T), fast=True)
         x = torch.view_as_complex(torch.from_numpy(st.x)).to(dev).contiguous()
         h = torch.from_numpy(st.h).to(dev)

@@ -86,7 +86,9 @@ enum {
 };
 
 /* Limits. */
-#define PFB_MAX_TAPS 64
+#define PFB_MAX_TAPS 1024        /* forward and FIR-only plans            */
+#define PFB_MAX_TAPS_WINDOW 64   /* register-window kernels; pfb_backward
+                                    and batched plans accept up to this   */
 #define PFB_MIN_FFT_CHANNELS 32
 #define PFB_MAX_FFT_CHANNELS 8192
 
@@ -97,7 +99,8 @@ typedef struct {
                           form 2^a 3^b 5^c 7^d (powers of two take the fused
                           paths, other sizes the split path with a
                           mixed-radix transform)                            */
-    int32_t taps;      /* T in [1, PFB_MAX_TAPS]                               */
+    int32_t taps;      /* T in [1, PFB_MAX_TAPS]; above PFB_MAX_TAPS_WINDOW the
+                          forward runs the long-tap FIR on the split path  */
     int64_t spectra;   /* S >= 1                                               */
     int32_t batch;     /* B >= 1 independent streams                           */
     int32_t dtype;     /* a pfb_dtype                                          */
@@ -187,7 +190,8 @@ pfb_status pfb_backward(pfb_plan *plan, const void *x, const float *taps, const 
 
 /*
  * Many independent beams with their own C, T, S (one stream each, complex
- * float32, C a power of two in [32, 8192], T <= 64) in one persistent launch
+ * float32, C a power of two in [32, 8192], T <= PFB_MAX_TAPS_WINDOW) in one
+ * persistent launch
  * per call, recorded into a HIP graph when the plan is created. Each beam's
  * result is the forward filter bank of its descriptor (Alg. 1 then Eq. (2)),
  * bit-identical to a separate single-beam plan.

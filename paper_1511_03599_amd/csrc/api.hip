@@ -100,6 +100,7 @@ struct pfb_plan {
     int64_t chunk_rows = 0;
     float2 *twiddle = nullptr;   // FFT twiddle table for C
     bool mixed = false;          // C not a power of two: mixed-radix transform
+    bool long_fir = false;       // T beyond the register window
     GfftSched gf{};
     float2 *ws_y = nullptr;      // filtered spectra workspace (split path)
     int64_t ws_y_bytes = 0;
@@ -292,6 +293,7 @@ static pfb_status plan_single(const pfb_desc *d, pfb_plan *p)
     p->d = *d;
     (void)hipGetDevice(&p->device);
     p->tp = padded_taps(d->taps);
+    p->long_fir = d->taps > PFB_MAX_TAPS_WINDOW;
     {
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, p->device) == hipSuccess && prop.multiProcessorCount > 0)
@@ -376,7 +378,7 @@ static pfb_status plan_single(const pfb_desc *d, pfb_plan *p)
             if (st != PFB_OK)
                 return st;
         }
-        if (d->dtype == PFB_C64) {
+        if (d->dtype == PFB_C64 && d->taps <= PFB_MAX_TAPS_WINDOW) {
             p->bwd_fused = !(d->flags & (PFB_NO_FUSE | PFB_PLAIN)) && fused_bwd_supported(p->tp, p->log2c);
             // at least 128 gx rows per tile (the T-1 halo rows are transformed
             // twice and every tile writes a tap-gradient partial)
@@ -479,6 +481,13 @@ static hipError_t run_fir(const pfb_plan *p, const void *x, const float *h, floa
     a.out_first = s_a;
     a.out_count = n;
     a.y_bstride = y_bstride;
+    if (p->long_fir) {
+        a.SB = 32;
+        a.n_tiles = (int)ceil_div(n, a.SB);
+        a.n_cchunks = (int)ceil_div(d.channels, 64);
+        a.shift = 0;
+        return launch_fir_long(a, d.dtype, st);
+    }
     return launch_fir(a, d.dtype, p->tp, p->fir_cpt, false, st);
 }
 
@@ -634,6 +643,8 @@ extern "C" pfb_status pfb_backward(pfb_plan *p, const void *x, const float *taps
     const pfb_desc &d = p->d;
     if (d.dtype != PFB_C64)
         return fail(PFB_E_UNSUPPORTED, "pfb_backward needs complex float32 input");
+    if (d.taps > PFB_MAX_TAPS_WINDOW)
+        return fail(PFB_E_UNSUPPORTED, "pfb_backward supports up to PFB_MAX_TAPS_WINDOW taps");
     if (!gY || !taps || (gh && !x))
         return fail(PFB_E_INVALID, "gY and taps (and x for gh) must be non-NULL");
     if (!aligned16(gY) || !aligned16(taps) || (x && !aligned16(x)) || (gx && !aligned16(gx)) ||

@@ -73,6 +73,9 @@ struct BwdArgs {
 };
 
 hipError_t launch_fir(const FirArgs &a, int dtype, int tp, int cpt, bool rev, hipStream_t st);
+// FIR for T beyond the register window: tiles of 32 rows (SB = 32), one
+// channel per lane (64 per wave task), no tap padding (shift = 0).
+hipError_t launch_fir_long(const FirArgs &a, int dtype, hipStream_t st);
 hipError_t launch_gh(const GhArgs &a, int tp, float *gh, hipStream_t st);
 hipError_t launch_fft(const FftArgs &a, int log2c, bool inv, hipStream_t st);
 

@@ -313,7 +313,7 @@ extern "C" pfb_status pfb_tune(const pfb_desc *desc, const char *cache_path)
     if (best_t < 0)
         return pfb_internal_fail(PFB_E_HIP, "no tuning candidate ran");
     // the adjoint's tile height, timed with the forward configuration chosen
-    if (!fir_only && d.dtype == PFB_C64) {
+    if (!fir_only && d.dtype == PFB_C64 && d.taps <= PFB_MAX_TAPS_WINDOW) {
         const size_t gxbytes = (size_t)(d.batch * rows * d.channels) * 8;
         if (hipMalloc(&buf.gx, gxbytes) == hipSuccess &&
             hipMalloc(&buf.gh, (size_t)d.taps * d.channels * 4) == hipSuccess &&

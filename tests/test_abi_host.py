@@ -55,7 +55,7 @@ def _create(L, **kw):
 
 @pytest.mark.parametrize("kw,code", [
     ({"channels": 0}, 1), ({"taps": 0}, 1), ({"spectra": 0}, 1), ({"batch": 0}, 1),
-    ({"taps": 65}, 2), ({"channels": 44}, 2), ({"channels": 16}, 2), ({"channels": 16384}, 2),
+    ({"taps": 1025}, 2), ({"channels": 44}, 2), ({"channels": 16}, 2), ({"channels": 16384}, 2),
     ({"channels": 8190}, 2), ({"channels": 13 * 64}, 2),
     ({"dtype": "c64", "flags": 1 << 10}, 1),
     ({"channels": 1 << 30, "spectra": 1 << 40, "flags": 1}, 1),

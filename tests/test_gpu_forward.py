@@ -92,7 +92,7 @@ def test_forward_parity_low_precision(dev, dtype, C, T):
 
 
 @pytest.mark.parametrize("mode", ["fir_only", "split_y"])
-@pytest.mark.parametrize("T", [1, 3, 8, 16, 37, 64])
+@pytest.mark.parametrize("T", [1, 3, 8, 16, 37, 64, 100, 200])
 def test_impulse_gives_reversed_taps_bit_exact(dev, mode, T):
     import torch
     pfb = pfbmod()
@@ -287,3 +287,33 @@ def test_non_smooth_channels_rejected(dev):
         pfb.Plan(8190, 4, 10)
     with pytest.raises(pfb.PFBError):
         pfb.BatchedPlan([(96, 4, 10)])
+
+
+@pytest.mark.parametrize("C,T,S,B,dtype", [(1024, 65, 100, 1, "c64"), (256, 96, 70, 2, "c64"),
+                                           (1000, 192, 40, 1, "c64"), (512, 257, 33, 1, "ci16"),
+                                           (128, 128, 300, 1, "ci8"), (3072, 100, 8, 1, "cf16")])
+def test_long_taps_fir_parity(dev, C, T, S, B, dtype):
+    """Taps beyond the register window (segmented long-tap FIR) against the
+    oracle's direct FIR, ragged tiles and channel chunks included."""
+    pfb = pfbmod()
+    say(f"long-tap FIR C={C} T={T} S={S} B={B} {dtype}")
+    x, h = make(C, T, S, B, dtype, 1500 + C + T)
+    plan = pfb.Plan(C, T, S, B, dtype, pfb.FIR_ONLY)
+    y = plan.execute(to_device(x, dev), taps_to_device(h, dev))
+    errs = rel_l2_per_stream(c128(y), oracle.fir(x, h))
+    assert max(errs) <= FIR_TOL, errs
+
+
+@pytest.mark.parametrize("C,T,S,B", [(1024, 192, 20, 1), (256, 300, 50, 2), (3072, 80, 6, 1)])
+def test_long_taps_pfb_parity(dev, C, T, S, B):
+    pfb = pfbmod()
+    say(f"long-tap PFB C={C} T={T} S={S} B={B}")
+    x, h = make(C, T, S, B, "c64", 1600 + C + T)
+    plan = pfb.Plan(C, T, S, B, "c64")
+    assert plan.info()["path"] == "split"
+    Y = plan.execute(to_device(x, dev), taps_to_device(h, dev))
+    errs = rel_l2_per_stream(c128(Y), oracle.pfb_forward(x, h))
+    assert max(errs) <= SPEC_TOL, errs
+    with pytest.raises(pfb.PFBError):
+        plan.backward(to_device(x, dev), taps_to_device(h, dev),
+                      to_device(synth.quantise(synth.complex_gaussian((B, S, C), 1601), "c64"), dev))
