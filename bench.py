@@ -248,6 +248,29 @@ def extras_mixed_radix(dev, stream):
     return out
 
 
+def extras_subbands(dev, stream):
+    """Polarisation-interleaved sub-band layout at the size of the paper's
+    spectrometer comparison: 2 * 4096 channels * 8 sub-bands = 65536 columns,
+    int8 samples, 2048 filtered spectra, T = 16 and 64."""
+    import torch
+    from paper_1511_03599_amd import pfb, synth
+    CV, NS, S = 4096, 8, 2048
+    out = {}
+    for T in (16, 64):
+        g = torch.Generator().manual_seed(1511600 + T)
+        x = torch.randint(-100, 100, (S + T - 1, NS, CV, 2, 2), dtype=torch.int8, generator=g).to(dev)
+        h = torch.from_numpy(synth.windowed_sinc_taps(CV, T)).to(dev)
+        p = pfb.VegasPlan(CV, NS, T, S, "ci8")
+        Y = torch.empty((S, NS, CV, 2), dtype=torch.complex64, device=dev)
+        for _ in range(2):
+            p.execute(x, h, Y=Y)
+        t = time_calls(lambda: p.execute(x, h, Y=Y), 10, stream)
+        samples = S * NS * CV * 2
+        out[str(T)] = {"ms": round(t, 4), "msamples_s": round(samples / t / 1e3, 1)}
+        del p, x, Y
+    return out
+
+
 def extras_differentiable(dev, stream):
     """32 streams x 8192 spectra, C=1024, T=16: forward, adjoint, and both."""
     import torch
@@ -385,6 +408,9 @@ def main():
         extras["differentiable_b32_s8192_c1024_t16"] = extras_differentiable(dev, stream)
         log("bench: mixed-radix channel counts")
         extras["mixed_radix_t16"] = extras_mixed_radix(dev, stream)
+        torch.cuda.empty_cache()
+        log("bench: sub-band layout")
+        extras["subbands_cv4096_n8_ci8"] = extras_subbands(dev, stream)
         torch.cuda.empty_cache()
         log("bench: streaming")
         extras["streaming_c1024_t16_ci16"] = extras_streaming(dev, stream)

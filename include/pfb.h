@@ -171,6 +171,29 @@ pfb_status pfb_execute_stream(pfb_plan *plan, void *xbuf, const float *taps, voi
 pfb_status pfb_stream_reset(pfb_plan *plan, void *stream);
 
 /*
+ * Polarisation-interleaved sub-band layout (as in the VEGAS spectrometer the
+ * paper compares with, Sec. 5): every raw spectrum holds `subbands`
+ * sub-bands of `channels` channels, each channel 2 interleaved complex
+ * polarisations: x [spectra+taps-1][subbands][channels][2] of `dtype`. The
+ * plan runs, for every sub-band and polarisation, the filter bank of Alg. 1
+ * and Eq. (2) over that sub-band's channels with the same C_V-channel taps:
+ * the FIR treats all 2*channels*subbands columns as independent channels
+ * (the mapping C = 2 C_V N_sub of Sec. 5), and the transform reads each
+ * polarisation of each sub-band with element stride 2.
+ *   channels  C_V, a power of two in [32, 8192]; subbands >= 1; taps as for
+ *             pfb_plan_create (T <= PFB_MAX_TAPS); dtype any pfb_dtype.
+ *   taps      device, [T][channels] float32 (replicated by the library)
+ *   Y         device, [spectra][subbands][channels][2] complex float32:
+ *             bin k of polarisation p of sub-band b at Y[s][b][k][p].
+ * The plan owns a filtered-spectra workspace (spectra*2*channels*subbands
+ * complex values) and the replicated taps. pfb_execute/pfb_backward reject
+ * these plans (PFB_E_STATE).
+ */
+pfb_status pfb_plan_create_vegas(int32_t channels, int32_t subbands, int32_t taps, int64_t spectra,
+                                 int32_t dtype, pfb_plan **out);
+pfb_status pfb_execute_vegas(pfb_plan *plan, const void *x, const float *taps, void *Y, void *stream);
+
+/*
  * Adjoint (backward) of the forward filter bank for a real loss, given
  * gY = dL/dRe(Y) + i dL/dIm(Y) (the frequency-spectra gradient):
  *   gy[b][s][c] = sum_m gY[b][s][m] exp(+2 pi i m c / C)   (adjoint of Eq. (2))

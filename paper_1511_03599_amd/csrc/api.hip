@@ -113,6 +113,11 @@ struct pfb_plan {
     bool bwd_ws = false;         // ... its wave-specialised form
     int bwd_sb = 256;            // gx rows per fused adjoint tile
     int num_cus = 256;           // compute units of the plan's device
+    // polarisation-interleaved sub-band layout: per spectrum vegas_nsub
+    // sub-bands of vegas_cv channels x 2 polarisations; d describes the FIR
+    // over all 2*cv*nsub columns (FIR_ONLY), h_rep holds the replicated taps
+    int vegas_cv = 0, vegas_nsub = 0, vegas_log2cv = -1;
+    float *h_rep = nullptr;
     // streaming: the last T-1 raw spectra of each stream, [B][T-1][C]
     char *hist = nullptr;
     int64_t hist_bytes = 0;
@@ -229,10 +234,13 @@ static void free_plan_memory(pfb_plan *p)
         (void)hipFree(p->ws_gh);
     if (p->hist)
         (void)hipFree(p->hist);
+    if (p->h_rep)
+        (void)hipFree(p->h_rep);
     p->twiddle = nullptr;
     p->ws_y = p->ws_gy = nullptr;
     p->ws_gh = nullptr;
     p->hist = nullptr;
+    p->h_rep = nullptr;
 }
 
 static pfb_status dev_alloc(void **p, int64_t bytes, const char *what)
@@ -513,7 +521,7 @@ static pfb_status check_execute_args(const pfb_plan *p, const void *x, const flo
 {
     if (!p)
         return fail(PFB_E_INVALID, "plan is NULL");
-    if (p->kind != KIND_SINGLE)
+    if (p->kind != KIND_SINGLE || p->vegas_cv > 0)
         return fail(PFB_E_STATE, "pfb_execute needs a single-problem plan");
     if (!x || !taps)
         return fail(PFB_E_INVALID, "x and taps must be non-NULL");
@@ -628,6 +636,85 @@ extern "C" pfb_status pfb_stream_reset(pfb_plan *p, void *stream)
 }
 
 // ----------------------------------------------------------------------------
+// Polarisation-interleaved sub-band layout
+// ----------------------------------------------------------------------------
+
+extern "C" pfb_status pfb_plan_create_vegas(int32_t channels, int32_t subbands, int32_t taps, int64_t spectra,
+                                            int32_t dtype, pfb_plan **out)
+{
+    if (!out)
+        return fail(PFB_E_INVALID, "out is NULL");
+    *out = nullptr;
+    const int l2 = ilog2_exact(channels);
+    if (l2 < 0 || channels < PFB_MIN_FFT_CHANNELS || channels > PFB_MAX_FFT_CHANNELS)
+        return fail(PFB_E_UNSUPPORTED, "channels per sub-band must be a power of two in [32, 8192]");
+    if (subbands < 1)
+        return fail(PFB_E_INVALID, "subbands must be >= 1");
+    int64_t cols = 0;
+    if (!mul_ok((int64_t)2 * channels, subbands, &cols) || cols > INT32_MAX)
+        return fail(PFB_E_INVALID, "2 * channels * subbands overflows");
+    pfb_desc d{};
+    d.channels = (int32_t)cols;
+    d.taps = taps;
+    d.spectra = spectra;
+    d.batch = 1;
+    d.dtype = dtype;
+    d.flags = PFB_FIR_ONLY;
+    pfb_status st = validate_desc(&d, false);
+    if (st != PFB_OK)
+        return st;
+    pfb_plan *p = new (std::nothrow) pfb_plan();
+    if (!p)
+        return fail(PFB_E_NOMEM, "host allocation of the plan failed");
+    st = plan_single(&d, p);
+    if (st == PFB_OK) {
+        p->vegas_cv = channels;
+        p->vegas_nsub = subbands;
+        p->vegas_log2cv = l2;
+        st = make_twiddles(l2, &p->twiddle);
+    }
+    if (st == PFB_OK) {
+        p->ws_y_bytes = spectra * cols * 8;
+        st = dev_alloc(reinterpret_cast<void **>(&p->ws_y), p->ws_y_bytes, "filtered spectra");
+    }
+    if (st == PFB_OK)
+        st = dev_alloc(reinterpret_cast<void **>(&p->h_rep), (int64_t)taps * cols * 4, "replicated taps");
+    if (st != PFB_OK) {
+        free_plan_memory(p);
+        delete p;
+        return st;
+    }
+    *out = p;
+    return PFB_OK;
+}
+
+extern "C" pfb_status pfb_execute_vegas(pfb_plan *p, const void *x, const float *taps, void *Y, void *stream)
+{
+    if (!p)
+        return fail(PFB_E_INVALID, "plan is NULL");
+    if (p->kind != KIND_SINGLE || p->vegas_cv <= 0)
+        return fail(PFB_E_STATE, "pfb_execute_vegas needs a plan from pfb_plan_create_vegas");
+    if (!x || !taps || !Y)
+        return fail(PFB_E_INVALID, "x, taps and Y must be non-NULL");
+    if (!aligned16(x) || !aligned16(taps) || !aligned16(Y))
+        return fail(PFB_E_INVALID, "device pointers must be 16-byte aligned");
+    const pfb_desc &d = p->d;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = launch_vegas_taps(taps, p->h_rep, d.taps, p->vegas_cv, p->vegas_nsub, st);
+    if (e == hipSuccess)
+        e = run_fir(p, x, p->h_rep, p->ws_y, 0, d.spectra, d.spectra * d.channels, st);
+    if (e == hipSuccess) {
+        FftArgs a{};
+        a.in = p->ws_y;
+        a.out = reinterpret_cast<float2 *>(Y);
+        a.tw = p->twiddle;
+        a.nrows = d.spectra * p->vegas_nsub * 2;
+        e = launch_fft_pol2(a, p->vegas_log2cv, st);
+    }
+    return e == hipSuccess ? PFB_OK : hip_fail(e, "sub-band filter bank launch");
+}
+
+// ----------------------------------------------------------------------------
 // Backward
 // ----------------------------------------------------------------------------
 
@@ -636,7 +723,7 @@ extern "C" pfb_status pfb_backward(pfb_plan *p, const void *x, const float *taps
 {
     if (!p)
         return fail(PFB_E_INVALID, "plan is NULL");
-    if (p->kind != KIND_SINGLE)
+    if (p->kind != KIND_SINGLE || p->vegas_cv > 0)
         return fail(PFB_E_STATE, "pfb_backward needs a single-problem plan");
     if (p->path == PATH_FIR_ONLY)
         return fail(PFB_E_STATE, "pfb_backward needs a plan with the FFT step");

@@ -42,6 +42,60 @@ __global__ __launch_bounds__(FftKernelShape<LOG2C>::NT, FftKernelShape<LOG2C>::M
         [&](int idx, float2 v) { store_nt(out + idx, v); });
 }
 
+// Transforms of polarisation-interleaved sub-bands (the VEGAS-style layout:
+// per spectrum, nsub sub-bands of C channels, each channel holding 2
+// interleaved polarisations). Row r = (s * nsub + sub) * 2 + pol transforms
+// the C elements at base + 2*idx, base = (s * nsub + sub) * 2C + pol, and
+// writes its bins to the same positions of out.
+template <int LOG2C, bool INV>
+__global__ __launch_bounds__(FftKernelShape<LOG2C>::NT, FftKernelShape<LOG2C>::MIN_WAVES) void fft_pol2_kernel(
+    FftArgs a)
+{
+    using K = FftKernelShape<LOG2C>;
+    constexpr int G = K::G;
+    constexpr int C = 1 << LOG2C;
+    using S = FftShape<LOG2C, G>;
+    __shared__ float2 lds[K::F * S::PADDED];
+    const int gid = (int)threadIdx.x / G;
+    const int lane = (int)threadIdx.x % G;
+    const int64_t row = (int64_t)blockIdx.x * K::F + gid;
+    if (row >= a.nrows)
+        return;
+    const int64_t base = (row >> 1) * 2 * C + (row & 1);
+    const float2 *in = a.in + base;
+    float2 *out = a.out + base;
+    fft_run<LOG2C, G, INV, false>(
+        lane, lds + gid * S::PADDED, a.tw, [&](int idx) { return in[2 * idx]; },
+        [&](int idx, float2 v) { store_nt(out + 2 * idx, v); });
+}
+
+hipError_t launch_fft_pol2(const FftArgs &a, int log2c, hipStream_t st)
+{
+    switch (log2c) {
+#define PFB_POL2_C(L2)                                                                                       \
+    case L2: {                                                                                               \
+        using K = FftKernelShape<L2>;                                                                        \
+        const int64_t blocks = (a.nrows + K::F - 1) / K::F;                                                  \
+        if (blocks <= 0)                                                                                     \
+            return hipSuccess;                                                                               \
+        hipLaunchKernelGGL((fft_pol2_kernel<L2, false>), dim3((unsigned)blocks), dim3(K::NT), 0, st, a);     \
+        return hipGetLastError();                                                                            \
+    }
+        PFB_POL2_C(5)
+        PFB_POL2_C(6)
+        PFB_POL2_C(7)
+        PFB_POL2_C(8)
+        PFB_POL2_C(9)
+        PFB_POL2_C(10)
+        PFB_POL2_C(11)
+        PFB_POL2_C(12)
+        PFB_POL2_C(13)
+#undef PFB_POL2_C
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
 template <int LOG2C> static hipError_t launch_fft_t(const FftArgs &a, bool inv, hipStream_t st)
 {
     using K = FftKernelShape<LOG2C>;

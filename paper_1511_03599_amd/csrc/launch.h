@@ -78,6 +78,13 @@ hipError_t launch_fir(const FirArgs &a, int dtype, int tp, int cpt, bool rev, hi
 hipError_t launch_fir_long(const FirArgs &a, int dtype, hipStream_t st);
 hipError_t launch_gh(const GhArgs &a, int tp, float *gh, hipStream_t st);
 hipError_t launch_fft(const FftArgs &a, int log2c, bool inv, hipStream_t st);
+// Forward transforms of polarisation-interleaved sub-bands: a.nrows =
+// spectra * nsub * 2 rows, row r at a.in + (r/2)*2C + (r%2), element stride 2
+// (a.rows_per_group and the group strides are not used).
+hipError_t launch_fft_pol2(const FftArgs &a, int log2c, hipStream_t st);
+// Replicate C_V-channel taps over polarisation-interleaved sub-bands:
+// out[t][(sub*cv + c)*2 + pol] = in[t][c].
+hipError_t launch_vegas_taps(const float *in, float *out, int T, int cv, int nsub, hipStream_t st);
 
 // Mixed-radix transform for C = 2^a 3^b 5^c 7^d (not a power of two).
 constexpr int GF_MAX_PASS = 16;

@@ -49,8 +49,9 @@ class PlanInfo(ctypes.Structure):
 
 
 EXPORTED = ("pfb_plan_create", "pfb_execute", "pfb_execute_stream", "pfb_stream_reset", "pfb_backward",
-            "pfb_plan_create_batched", "pfb_execute_batched", "pfb_tune", "pfb_tune_batched",
-            "pfb_plan_get_info", "pfb_plan_destroy", "pfb_status_str", "pfb_last_error")
+            "pfb_plan_create_batched", "pfb_execute_batched", "pfb_plan_create_vegas", "pfb_execute_vegas",
+            "pfb_tune", "pfb_tune_batched", "pfb_plan_get_info", "pfb_plan_destroy", "pfb_status_str",
+            "pfb_last_error")
 
 _lib = None
 
@@ -69,6 +70,8 @@ def lib():
     L.pfb_execute.argtypes = [vp, vp, vp, vp, vp, vp]
     L.pfb_execute_stream.argtypes = [vp, vp, vp, vp, vp, vp]
     L.pfb_stream_reset.argtypes = [vp, vp]
+    L.pfb_plan_create_vegas.argtypes = [i32, i32, i32, ctypes.c_int64, i32, ctypes.POINTER(vp)]
+    L.pfb_execute_vegas.argtypes = [vp, vp, vp, vp, vp]
     L.pfb_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.pfb_plan_create_batched.argtypes = [i32, ctypes.POINTER(Desc), ctypes.POINTER(vp)]
     L.pfb_execute_batched.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
@@ -81,8 +84,8 @@ def lib():
     L.pfb_last_error.argtypes = []
     L.pfb_last_error.restype = ctypes.c_char_p
     for f in ("pfb_plan_create", "pfb_execute", "pfb_execute_stream", "pfb_stream_reset", "pfb_backward",
-              "pfb_plan_create_batched", "pfb_execute_batched", "pfb_tune", "pfb_tune_batched",
-              "pfb_plan_get_info", "pfb_plan_destroy"):
+              "pfb_plan_create_batched", "pfb_execute_batched", "pfb_plan_create_vegas", "pfb_execute_vegas",
+              "pfb_tune", "pfb_tune_batched", "pfb_plan_get_info", "pfb_plan_destroy"):
         getattr(L, f).restype = st
     _lib = L
     return L
@@ -278,6 +281,42 @@ class BatchedPlan:
         Ya = P(*[Y.data_ptr() for Y in Ys])
         check(lib().pfb_execute_batched(self._h, xa, ha, Ya, _stream(stream)))
         return Ys
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pfb_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class VegasPlan:
+    """Polarisation-interleaved sub-bands: x [S+T-1, nsub, C, 2] (+ trailing
+    re/im axis for integer and float16 types) -> Y complex64 [S, nsub, C, 2],
+    one C-channel filter bank per sub-band and polarisation with the same
+    taps h [T, C]."""
+
+    def __init__(self, channels, subbands, taps, spectra, dtype="c64"):
+        self.C, self.NS, self.T, self.S = int(channels), int(subbands), int(taps), int(spectra)
+        self.dtype = dtype
+        h = ctypes.c_void_p()
+        check(lib().pfb_plan_create_vegas(self.C, self.NS, self.T, self.S, DTYPE_CODES[dtype], ctypes.byref(h)))
+        self._h = h
+
+    def execute(self, x, h, Y=None, stream=None):
+        want = (self.S + self.T - 1, self.NS, self.C, 2)
+        if not x.is_cuda or tuple(x.shape[:4]) != want or not x.is_contiguous():
+            raise PFBError(PFB_E_INVALID, f"x must be a contiguous CUDA tensor of shape {want}(+2)")
+        if not h.is_cuda or h.dtype != torch.float32 or tuple(h.shape) != (self.T, self.C) or not h.is_contiguous():
+            raise PFBError(PFB_E_INVALID, f"taps must be contiguous float32 CUDA [{self.T}, {self.C}]")
+        if Y is None:
+            Y = torch.empty((self.S, self.NS, self.C, 2), dtype=torch.complex64, device=x.device)
+        check(lib().pfb_execute_vegas(self._h, _ptr(x), _ptr(h), _ptr(Y), _stream(stream)))
+        return Y
 
     def close(self):
         if getattr(self, "_h", None):

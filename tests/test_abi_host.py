@@ -30,7 +30,7 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for want in ("pfb_plan_create", "pfb_execute", "pfb_backward", "pfb_plan_create_batched",
                  "pfb_execute_batched", "pfb_tune", "pfb_tune_batched", "pfb_plan_destroy", "pfb_status_str",
-                 "pfb_execute_stream", "pfb_stream_reset",
+                 "pfb_execute_stream", "pfb_stream_reset", "pfb_plan_create_vegas", "pfb_execute_vegas",
                  "pfb_last_error", "pfb_plan_get_info"):
         assert want in names
 
@@ -80,6 +80,11 @@ def test_null_arguments(L):
     assert L.pfb_backward(None, None, None, None, None, None, None) == 1
     assert L.pfb_execute_stream(None, None, None, None, None, None) == 1
     assert L.pfb_stream_reset(None, None) == 1
+    assert L.pfb_execute_vegas(None, None, None, None, None) == 1
+    h = ctypes.c_void_p()
+    assert L.pfb_plan_create_vegas(48, 2, 4, 10, 0, ctypes.byref(h)) == 2    # C_V not a power of two
+    assert L.pfb_plan_create_vegas(64, 0, 4, 10, 0, ctypes.byref(h)) == 1    # no sub-band
+    assert L.pfb_plan_create_vegas(64, 2, 0, 10, 0, ctypes.byref(h)) == 1    # no tap
     assert L.pfb_plan_destroy(None) == 0
     assert L.pfb_status_str(0) == b"PFB_OK"
     assert b"INVALID" in L.pfb_status_str(1)
