@@ -5,6 +5,7 @@
 // call. Every step of the computation runs in the HIP kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -284,6 +285,15 @@ static int balanced_tile_rows(int64_t B, int64_t rows, int rb, int64_t min_rows,
     return (int)best_sb;
 }
 
+// Largest tile height (a multiple of rb) whose rows plus `extra` halo rows
+// fit one bounded view (under 2 GiB) at row_bytes per row: the fused adjoint
+// addresses a tile's rows through such views.
+static int view_rows_cap(int64_t row_bytes, int rb, int extra)
+{
+    const int64_t cap = ((int64_t)0x7fffffff / row_bytes - extra) / rb * rb;
+    return (int)(cap < rb ? rb : (cap > INT32_MAX ? INT32_MAX / rb * rb : cap));
+}
+
 // Rows per fused tile: short tiles (four chunks) so that many workgroups
 // run in launch order and the resident ones sweep a narrow band of rows; the
 // halo rows they share with the previous tile are then still cached.
@@ -393,6 +403,7 @@ static pfb_status plan_single(const pfb_desc *d, pfb_plan *p)
             p->bwd_sb = balanced_tile_rows(d->batch, d->spectra + d->taps - 1, 16, 128, p->num_cus);
             if (tuned && te.bwd_sb >= 16 && te.bwd_sb <= 65536)
                 p->bwd_sb = te.bwd_sb;
+            p->bwd_sb = std::min(p->bwd_sb, view_rows_cap((int64_t)d->channels * 8, 16, 0));
             // measured: the single-role adjoint is the faster default at
             // every supported size (the tuner may still pick the other)
             p->bwd_ws = false;

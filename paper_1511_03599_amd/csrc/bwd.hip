@@ -66,8 +66,10 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_bwd_kernel(BwdArgs a
     enum { TAIL = 0, FULL = 1, LAST = 2 };
     // the untested chunk form needs registers the 16-tap, two-channel
     // window does not leave (it spills, and every reload waits for all
-    // memory operations): that variant tests each row
+    // memory operations): that variant runs every row unconditionally
+    // through bounded views instead (BUF below)
     constexpr bool EXACT = !(TP >= 16 && CPT == 2);
+    constexpr bool BUF = !EXACT;
 
     // window slot j of output p holds gy[p - (TP-1) + j], tap t = TP-1-j
     float hp[TP][CPT];
@@ -88,12 +90,30 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_bwd_kernel(BwdArgs a
             sfor<CPT>([&](auto k) { o[k] = make_float2(0.0f, 0.0f); });
     };
 
+    // BUF: bounded views of this tile's x and gx rows [p0, p0 + np); row o
+    // of the tile starts at byte o*C*8. Rows outside (o < 0 while the window
+    // fills, o >= np past the tile or the stream) read as zeros and are not
+    // written, so the walk needs no test. Unsigned offset arithmetic: a
+    // negative o wraps beyond any range.
+    const int64_t tile_bytes = (int64_t)np * C * 8;
+    const BufView vx = buf_view(xb + p0 * C, want_gh ? tile_bytes : 0);
+    const BufView vgx = buf_view(want_gx ? gxb + p0 * C : xb, want_gx ? tile_bytes : 0);
+    const uint32_t lane_off = (uint32_t)c0 * 8u;
+    auto row_off = [&](int o) { return (int)((uint32_t)o * (uint32_t)(C * 8) + lane_off); };
+
     float2 w[TP][CPT];
-    float2 pf[D][CPT]; // x rows p0 + k, prefetched
-    sfor<D>([&](auto k) {
-        if (k < np)
-            ldx(p0 + k, pf[k]);
-    });
+    float2 pf[D][CPT]; // prefetched x rows: p0 + k (BUF: p0 - (TP-1) + k)
+    if constexpr (BUF) {
+        // the window's unfilled slots must hold finite values: rows o < 0
+        // add their products with zero x rows to the tap-gradient sums
+        sfor<TP>([&](auto j) { sfor<CPT>([&](auto k) { w[j][k] = make_float2(0.0f, 0.0f); }); });
+        sfor<D>([&](auto k) { buf_load_c64<CPT>(vx, row_off((int)k - (TP - 1)), pf[k]); });
+    } else {
+        sfor<D>([&](auto k) {
+            if (k < np)
+                ldx(p0 + k, pf[k]);
+        });
+    }
 
     const int gid = t / G;
     const int lane = t % G;
@@ -191,8 +211,36 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_bwd_kernel(BwdArgs a
                 }
             });
         };
-        if (EXACT && both && base >= TP - 1 && base + RB <= nq && base + RB - TP + D < np)
-            grad_chunk(std::integral_constant<int, EXACT ? FULL : TAIL>{});
+        // BUF form: gy row q0 + i with i = base + jj serves output row
+        // o = i - (TP-1); x row o is taken from prefetch slot jj mod D and
+        // row o + D loaded into it. Every load and store is issued.
+        auto grad_buf = [&]() PFB_INLINE {
+            sfor<RB>([&](auto jjc) PFB_INLINE {
+                constexpr int jj = decltype(jjc)::value;
+                const int o = base + jj - (TP - 1);
+                sfor<CPT>([&](auto k) PFB_INLINE { w[jj % TP][k] = lds[jj * S::PADDED + S::pad(c0 + k)]; });
+                float2 xv[CPT];
+                sfor<CPT>([&](auto k) PFB_INLINE { xv[k] = pf[jj % D][k]; });
+                buf_load_c64<CPT>(vx, row_off(o + D), pf[jj % D]);
+                float2 g[CPT];
+                sfor<CPT>([&](auto k) PFB_INLINE {
+                    float gr = 0.0f, gi = 0.0f;
+                    sfor<TP>([&](auto jc) PFB_INLINE {
+                        constexpr int j = decltype(jc)::value;
+                        const float2 v = w[(jj + 1 + j) % TP][k];
+                        gr = __builtin_fmaf(hp[j][k], v.x, gr);
+                        gi = __builtin_fmaf(hp[j][k], v.y, gi);
+                        acc[j][k] = __builtin_fmaf(v.x, xv[k].x, __builtin_fmaf(v.y, xv[k].y, acc[j][k]));
+                    });
+                    g[k] = make_float2(gr, gi);
+                });
+                buf_store_c64_nt<CPT>(vgx, row_off(o), g);
+            });
+        };
+        if constexpr (BUF)
+            grad_buf();
+        else if (both && base >= TP - 1 && base + RB <= nq && base + RB - TP + D < np)
+            grad_chunk(std::integral_constant<int, FULL>{});
         else
             grad_chunk(std::integral_constant<int, TAIL>{});
         lds_barrier();

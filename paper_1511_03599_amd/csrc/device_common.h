@@ -45,8 +45,18 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// A wave-uniform pointer, moved into scalar registers. Row bases of an
-// unrolled block computed through this stay one scalar value per block:
+// A pointer known to address global memory. Device functions that are not
+// inlined receive plain (generic) pointers, whose accesses the compiler must
+// issue as flat instructions; rebuilding the pointer in the global address
+// space lets it use global loads and stores again. (A flat load also counts
+// against the LDS counter, so a wait for it drains the LDS traffic as well.)
+template <typename T> __device__ __forceinline__ T *as_global(T *p)
+{
+    return (T *)(__attribute__((address_space(1))) T *)(uintptr_t)p;
+}
+
+// A wave-uniform global pointer, moved into scalar registers. Row bases of
+// an unrolled block computed through this stay one scalar value per block:
 // otherwise loop strength reduction keeps one 64-bit vector induction
 // variable per unrolled row, which exhausts the registers.
 template <typename T> __device__ __forceinline__ T *wave_uniform(T *p)
@@ -54,16 +64,7 @@ template <typename T> __device__ __forceinline__ T *wave_uniform(T *p)
     const uint64_t v = (uint64_t)(uintptr_t)p;
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return (T *)(uintptr_t)(((uint64_t)hi << 32) | lo);
-}
-
-// A pointer known to address global memory. Device functions that are not
-// inlined receive plain (generic) pointers, whose accesses the compiler must
-// issue as flat instructions; rebuilding the pointer in the global address
-// space lets it use global loads and stores again.
-template <typename T> __device__ __forceinline__ T *as_global(T *p)
-{
-    return (T *)(__attribute__((address_space(1))) T *)(uintptr_t)p;
+    return as_global((T *)(uintptr_t)(((uint64_t)hi << 32) | lo));
 }
 
 template <int DT> struct SampleBytes;
@@ -224,6 +225,89 @@ __device__ __forceinline__ void store_c64(float2 *p, const float2 (&v)[V])
     } else {
         reinterpret_cast<float4 *>(p)[0] = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
         reinterpret_cast<float4 *>(p)[1] = make_float4(v[2].x, v[2].y, v[3].x, v[3].y);
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Bounded views: a byte range [base, base + bytes) of global memory (a raw
+// buffer resource, bytes < 2^31) addressed by 32-bit byte offsets. An access
+// whose offset lies outside the range is dropped by the memory unit: a load
+// returns zeros without touching memory, a store writes nothing. A negative
+// offset, taken as unsigned, is outside too. Kernels use views to issue every
+// load and store of a row unconditionally, with rows beyond a tile or a
+// stream simply falling outside the range: no memory operation then sits
+// under a branch, so the compiler knows how many are in flight and waits for
+// exactly the one a value comes from. The whole offset goes in the vector
+// offset operand (the scalar one is 0), so the range check covers all of it.
+// base and bytes must be wave-uniform.
+// ----------------------------------------------------------------------------
+
+struct BufView {
+    __amdgpu_buffer_rsrc_t r;
+};
+
+// Word 3 of a gfx9 raw buffer resource (32-bit data format, no swizzle).
+constexpr int BUF_WORD3 = 0x00020000;
+
+__device__ __forceinline__ BufView buf_view(const void *base, int64_t bytes)
+{
+    const int n = bytes <= 0 ? 0 : (bytes > 0x7fffffff ? 0x7fffffff : (int)bytes);
+    return {__builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, n, BUF_WORD3)};
+}
+
+typedef unsigned int v2u_t __attribute__((ext_vector_type(2)));
+typedef unsigned int v4u_t __attribute__((ext_vector_type(4)));
+
+// Cache-policy bits of a buffer access: non-temporal.
+constexpr int BUF_NT = 2;
+
+// Load a packed fragment of V samples at byte offset `off` of view `v`.
+template <int DT, int V> __device__ __forceinline__ void buf_load_packed(const BufView &v, int off, Packed<DT, V> &p)
+{
+    constexpr int B = V * SampleBytes<DT>::value;
+    if constexpr (B == 2) {
+        p.w[0] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(v.r, off, 0, 0);
+    } else if constexpr (B == 4) {
+        p.w[0] = __builtin_amdgcn_raw_buffer_load_b32(v.r, off, 0, 0);
+    } else if constexpr (B == 8) {
+        const v2u_t q = __builtin_amdgcn_raw_buffer_load_b64(v.r, off, 0, 0);
+        p.w[0] = q.x;
+        p.w[1] = q.y;
+    } else {
+        static_assert(B % 16 == 0, "fragment size");
+#pragma unroll
+        for (int k = 0; k < B / 16; ++k) {
+            const v4u_t q = __builtin_amdgcn_raw_buffer_load_b128(v.r, off + 16 * k, 0, 0);
+            p.w[4 * k] = q.x;
+            p.w[4 * k + 1] = q.y;
+            p.w[4 * k + 2] = q.z;
+            p.w[4 * k + 3] = q.w;
+        }
+    }
+}
+
+// Load V complex float32 values at byte offset `off` of view `v`.
+template <int V> __device__ __forceinline__ void buf_load_c64(const BufView &v, int off, float2 (&o)[V])
+{
+    Packed<DT_C64, V> p;
+    buf_load_packed<DT_C64, V>(v, off, p);
+    unpack<DT_C64, V>(p, o);
+}
+
+// Streaming (non-temporal) store of V complex float32 values at byte offset
+// `off` of view `v`.
+template <int V> __device__ __forceinline__ void buf_store_c64_nt(const BufView &v, int off, const float2 (&x)[V])
+{
+    if constexpr (V == 1) {
+        const v2u_t q = {__float_as_uint(x[0].x), __float_as_uint(x[0].y)};
+        __builtin_amdgcn_raw_buffer_store_b64(q, v.r, off, 0, BUF_NT);
+    } else {
+#pragma unroll
+        for (int k = 0; k < V; k += 2) {
+            const v4u_t q = {__float_as_uint(x[k].x), __float_as_uint(x[k].y), __float_as_uint(x[k + 1].x),
+                             __float_as_uint(x[k + 1].y)};
+            __builtin_amdgcn_raw_buffer_store_b128(q, v.r, off + 8 * k, 0, BUF_NT);
+        }
     }
 }
 

@@ -180,9 +180,12 @@ __device__ __forceinline__ void fft_passes(int lane, float2 *lds, const float2 *
     constexpr int E = S::E;
     // Opaque copy of the twiddle pointer: keeps the compiler from hoisting
     // the twiddle loads of every pass out of a caller's loop over rows, which
-    // would hold them all in registers at once.
-    const float2 *twp = tw;
-    asm volatile("" : "+v"(twp));
+    // would hold them all in registers at once. The copy is rebuilt as a
+    // global pointer: the opaque value has lost its address space, and flat
+    // loads would also count against the LDS counter.
+    const float2 *twp_opaque = tw;
+    asm volatile("" : "+v"(twp_opaque));
+    const float2 *twp = as_global(twp_opaque);
 
     sfor<S::NPASS>([&](auto pp) PFB_INLINE {
         constexpr int P = decltype(pp)::value;
