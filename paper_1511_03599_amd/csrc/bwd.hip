@@ -90,24 +90,20 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_bwd_kernel(BwdArgs a
             sfor<CPT>([&](auto k) { o[k] = make_float2(0.0f, 0.0f); });
     };
 
-    // BUF: bounded views of this tile's x and gx rows [p0, p0 + np); row o
-    // of the tile starts at byte o*C*8. Rows outside (o < 0 while the window
-    // fills, o >= np past the tile or the stream) read as zeros and are not
-    // written, so the walk needs no test. Unsigned offset arithmetic: a
-    // negative o wraps beyond any range.
-    const int64_t tile_bytes = (int64_t)np * C * 8;
-    const BufView vx = buf_view(xb + p0 * C, want_gh ? tile_bytes : 0);
-    const BufView vgx = buf_view(want_gx ? gxb + p0 * C : xb, want_gx ? tile_bytes : 0);
+    // BUF: every x load and gx store goes through a view of its one row
+    // (empty for rows outside the tile, o < 0 or o >= np), so the walk needs
+    // no test; the lane's offset in a row is the same for every row.
     const uint32_t lane_off = (uint32_t)c0 * 8u;
-    auto row_off = [&](int o) { return (int)((uint32_t)o * (uint32_t)(C * 8) + lane_off); };
 
     float2 w[TP][CPT];
     float2 pf[D][CPT]; // prefetched x rows: p0 + k (BUF: p0 - (TP-1) + k)
     if constexpr (BUF) {
         // the window's unfilled slots must hold finite values: rows o < 0
         // add their products with zero x rows to the tap-gradient sums
+        // (the ring starts at x rows o = -(TP-1) .. D-TP, all before the tile)
+        static_assert(D <= TP - 1, "prefetch ring starts before the tile");
         sfor<TP>([&](auto j) { sfor<CPT>([&](auto k) { w[j][k] = make_float2(0.0f, 0.0f); }); });
-        sfor<D>([&](auto k) { buf_load_c64<CPT>(vx, row_off((int)k - (TP - 1)), pf[k]); });
+        sfor<D>([&](auto j) { sfor<CPT>([&](auto k) { pf[j][k] = make_float2(0.0f, 0.0f); }); });
     } else {
         sfor<D>([&](auto k) {
             if (k < np)
@@ -136,6 +132,113 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_bwd_kernel(BwdArgs a
             sfor<E>([&](auto e) PFB_INLINE { gv[e] = make_float2(0.0f, 0.0f); });
         }
     };
+    if constexpr (BUF) {
+        // Every row through bounded views, and the two transform rounds of
+        // a chunk interleaved with its gradient rows:
+        //   round 0 (walk rows base..base+7) -> barrier -> gradient rows 0-7,
+        //   round 1 (rows base+8..base+15)   -> barrier -> gradient rows 8-15.
+        // Each round's gY loads are issued GAT gradient rows before the round
+        // starts (into gv, which the gradient rows leave room for), so their
+        // latency hides behind those rows. A round writes LDS rows that no
+        // wave reads until the barrier after it, and the rows it overwrites
+        // were last read before the previous barrier, so one barrier per
+        // round suffices.
+        static_assert(F::ROUNDS == 2 && F::NG * 2 == RB, "two transform rounds per chunk");
+        constexpr int HALF = RB / 2;
+        constexpr int GAT0 = HALF / 2, GAT1 = 0;
+        const int gw = __builtin_amdgcn_readfirstlane(gid); // this wave's transform
+        // first-pass inputs of walk row i (gy row q0 + i), through a view of
+        // that one row: rows outside [0, S) or past the walk read as zeros.
+        // (One view per row keeps every load's offset the lane's own
+        // constant, so no per-row offsets occupy vector registers.)
+        auto gather_buf = [&](int i) PFB_INLINE {
+            const int64_t q = q0 + i;
+            const bool ok = q >= 0 && q < a.S && i < nq;
+            const BufView vrow = buf_view(ok ? gYb + q * C : gYb, ok ? C * 8 : 0);
+            // the lane's byte offset, opaque so that the per-element offsets
+            // (lane offset plus a constant) are formed here and not kept in
+            // registers across the loop
+            int l8 = lane * 8;
+            asm volatile("" : "+v"(l8));
+            fft_gather_first<LOG2C, G, true>(
+                lane,
+                [&](int idx) {
+                    float2 o[1];
+                    buf_load_c64<1>(vrow, l8 + (idx - lane) * 8, o);
+                    return o[0];
+                },
+                gv);
+        };
+        // gradient row jj of the chunk at walk row base: gy row q0 + base + jj
+        // serves output row o = base + jj - (TP-1); x row o comes from
+        // prefetch slot jj mod D and row o + D is loaded into it
+        auto grad_row = [&](int base, auto jjc) PFB_INLINE {
+            constexpr int jj = decltype(jjc)::value;
+            const int o = base + jj - (TP - 1);
+            sfor<CPT>([&](auto k) PFB_INLINE { w[jj % TP][k] = lds[jj * S::PADDED + S::pad(c0 + k)]; });
+            float2 xv[CPT];
+            sfor<CPT>([&](auto k) PFB_INLINE { xv[k] = pf[jj % D][k]; });
+            {
+                const int ox = o + D;
+                const bool ok = want_gh && ox >= 0 && ox < np;
+                buf_load_c64<CPT>(buf_view(ok ? xb + (p0 + ox) * C : xb, ok ? C * 8 : 0), (int)lane_off, pf[jj % D]);
+            }
+            float2 g[CPT];
+            sfor<CPT>([&](auto k) PFB_INLINE {
+                float gr = 0.0f, gi = 0.0f;
+                sfor<TP>([&](auto jc) PFB_INLINE {
+                    constexpr int j = decltype(jc)::value;
+                    const float2 v = w[(jj + 1 + j) % TP][k];
+                    gr = __builtin_fmaf(hp[j][k], v.x, gr);
+                    gi = __builtin_fmaf(hp[j][k], v.y, gi);
+                    acc[j][k] = __builtin_fmaf(v.x, xv[k].x, __builtin_fmaf(v.y, xv[k].y, acc[j][k]));
+                });
+                g[k] = make_float2(gr, gi);
+            });
+            {
+                const bool ok = want_gx && o >= 0 && o < np;
+                buf_store_c64_nt<CPT>(buf_view(ok ? gxb + (p0 + o) * C : xb, ok ? C * 8 : 0), (int)lane_off, g);
+            }
+        };
+        // Across a round only the window rows that its transforms overwrite
+        // stay in registers: the other half of the window is still in LDS
+        // (the previous round's rows) and is read back after the round, so
+        // those registers are free during the transforms. Before the first
+        // chunk the second-half LDS rows hold zeros (the window's
+        // not-yet-walked rows).
+        sfor<HALF>([&](auto r) PFB_INLINE {
+            sfor<CPT>([&](auto k) PFB_INLINE {
+                lds[(HALF + decltype(r)::value) * S::PADDED + S::pad(c0 + k)] = make_float2(0.0f, 0.0f);
+            });
+        });
+        gather_buf(gw);
+        for (int base = 0; base < nq; base += RB) {
+            sfor<2>([&](auto hc) PFB_INLINE {
+                constexpr int H = decltype(hc)::value;
+                float2 cur[E];
+                sfor<E>([&](auto e) PFB_INLINE { cur[e] = gv[e]; });
+                float2 *row = lds + (H * F::NG + gw) * S::PADDED;
+                // opaque lane index: the transform's LDS addresses are then
+                // formed in each round instead of being hoisted out of the
+                // loop and held in registers for both rounds
+                int ln = lane;
+                asm volatile("" : "+v"(ln));
+                fft_passes<LOG2C, G, true, false>(ln, row, a.tw, cur,
+                                                  [&](int idx, float2 v) { row[S::pad(idx)] = v; });
+                lds_barrier();
+                // window slots of the half this round did not overwrite
+                sfor<HALF>([&](auto rc) PFB_INLINE {
+                    constexpr int r = (1 - H) * HALF + decltype(rc)::value;
+                    sfor<CPT>([&](auto k) PFB_INLINE { w[r][k] = lds[r * S::PADDED + S::pad(c0 + k)]; });
+                });
+                sfor<HALF>([&](auto jc) PFB_INLINE {
+                    grad_row(base, std::integral_constant<int, H * HALF + decltype(jc)::value>{});
+                    if constexpr (decltype(jc)::value == (H == 0 ? GAT0 : GAT1))
+                        gather_buf(H == 0 ? base + F::NG + gw : base + RB + gw);
+                });
+            });
+        }
+    } else {
     if constexpr (AHEAD)
         gather(0, 0);
     for (int base = 0; base < nq; base += RB) {
@@ -211,39 +314,12 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_bwd_kernel(BwdArgs a
                 }
             });
         };
-        // BUF form: gy row q0 + i with i = base + jj serves output row
-        // o = i - (TP-1); x row o is taken from prefetch slot jj mod D and
-        // row o + D loaded into it. Every load and store is issued.
-        auto grad_buf = [&]() PFB_INLINE {
-            sfor<RB>([&](auto jjc) PFB_INLINE {
-                constexpr int jj = decltype(jjc)::value;
-                const int o = base + jj - (TP - 1);
-                sfor<CPT>([&](auto k) PFB_INLINE { w[jj % TP][k] = lds[jj * S::PADDED + S::pad(c0 + k)]; });
-                float2 xv[CPT];
-                sfor<CPT>([&](auto k) PFB_INLINE { xv[k] = pf[jj % D][k]; });
-                buf_load_c64<CPT>(vx, row_off(o + D), pf[jj % D]);
-                float2 g[CPT];
-                sfor<CPT>([&](auto k) PFB_INLINE {
-                    float gr = 0.0f, gi = 0.0f;
-                    sfor<TP>([&](auto jc) PFB_INLINE {
-                        constexpr int j = decltype(jc)::value;
-                        const float2 v = w[(jj + 1 + j) % TP][k];
-                        gr = __builtin_fmaf(hp[j][k], v.x, gr);
-                        gi = __builtin_fmaf(hp[j][k], v.y, gi);
-                        acc[j][k] = __builtin_fmaf(v.x, xv[k].x, __builtin_fmaf(v.y, xv[k].y, acc[j][k]));
-                    });
-                    g[k] = make_float2(gr, gi);
-                });
-                buf_store_c64_nt<CPT>(vgx, row_off(o), g);
-            });
-        };
-        if constexpr (BUF)
-            grad_buf();
-        else if (both && base >= TP - 1 && base + RB <= nq && base + RB - TP + D < np)
+        if (both && base >= TP - 1 && base + RB <= nq && base + RB - TP + D < np)
             grad_chunk(std::integral_constant<int, FULL>{});
         else
             grad_chunk(std::integral_constant<int, TAIL>{});
         lds_barrier();
+    }
     }
     if (want_gh) {
         float *pb = a.part + ((int64_t)b * a.n_tiles + tile) * (int64_t)a.T * C + c0;

@@ -215,7 +215,8 @@ __device__ __forceinline__ void fft_passes(int lane, float2 *lds, const float2 *
             const int j = lane + G * Q;
             if constexpr (L > 1) {
                 const int k = j & (L - 1);
-                const float4 *wp = reinterpret_cast<const float4 *>(twp + S::pass_offset(P) + k * R);
+                constexpr int PO = S::pass_offset(P);
+                const float4 *wp = reinterpret_cast<const float4 *>(twp + PO + k * R);
                 sfor<R / 2>([&](auto hh) PFB_INLINE {
                     constexpr int H = decltype(hh)::value;
                     const float4 w2 = wp[H];
