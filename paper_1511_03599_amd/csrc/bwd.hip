@@ -69,7 +69,7 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_bwd_kernel(BwdArgs a
     // memory operations): that variant runs every row unconditionally
     // through bounded views instead (BUF below)
     constexpr bool EXACT = !(TP >= 16 && CPT == 2);
-    constexpr bool BUF = !EXACT;
+    constexpr bool BUF = CPT == 2;
 
     // window slot j of output p holds gy[p - (TP-1) + j], tap t = TP-1-j
     float hp[TP][CPT];
@@ -100,10 +100,13 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_bwd_kernel(BwdArgs a
     if constexpr (BUF) {
         // the window's unfilled slots must hold finite values: rows o < 0
         // add their products with zero x rows to the tap-gradient sums
-        // (the ring starts at x rows o = -(TP-1) .. D-TP, all before the tile)
-        static_assert(D <= TP - 1, "prefetch ring starts before the tile");
+        // the ring starts at x rows o = -(TP-1) .. D-TP (zeros before the tile)
         sfor<TP>([&](auto j) { sfor<CPT>([&](auto k) { w[j][k] = make_float2(0.0f, 0.0f); }); });
-        sfor<D>([&](auto j) { sfor<CPT>([&](auto k) { pf[j][k] = make_float2(0.0f, 0.0f); }); });
+        sfor<D>([&](auto j) {
+            const int o = (int)j - (TP - 1);
+            const bool ok = want_gh && o >= 0 && o < np;
+            buf_load_c64<CPT>(buf_view(ok ? xb + (p0 + o) * C : xb, ok ? C * 8 : 0), (int)lane_off, pf[j]);
+        });
     } else {
         sfor<D>([&](auto k) {
             if (k < np)
@@ -226,10 +229,12 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_bwd_kernel(BwdArgs a
                 fft_passes<LOG2C, G, true, false>(ln, row, a.tw, cur,
                                                   [&](int idx, float2 v) { row[S::pad(idx)] = v; });
                 lds_barrier();
-                // window slots of the half this round did not overwrite
-                sfor<HALF>([&](auto rc) PFB_INLINE {
-                    constexpr int r = (1 - H) * HALF + decltype(rc)::value;
-                    sfor<CPT>([&](auto k) PFB_INLINE { w[r][k] = lds[r * S::PADDED + S::pad(c0 + k)]; });
+                // window slots holding rows of the half this round did not
+                // overwrite (the last min(TP, HALF) rows of that half)
+                constexpr int NRR = TP < HALF ? TP : HALF;
+                sfor<NRR>([&](auto rc) PFB_INLINE {
+                    constexpr int r = (1 - H) * HALF + HALF - NRR + decltype(rc)::value;
+                    sfor<CPT>([&](auto k) PFB_INLINE { w[r % TP][k] = lds[r * S::PADDED + S::pad(c0 + k)]; });
                 });
                 sfor<HALF>([&](auto jc) PFB_INLINE {
                     grad_row(base, std::integral_constant<int, H * HALF + decltype(jc)::value>{});
