@@ -69,7 +69,7 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_bwd_kernel(BwdArgs a
     // memory operations): that variant runs every row unconditionally
     // through bounded views instead (BUF below)
     constexpr bool EXACT = !(TP >= 16 && CPT == 2);
-    constexpr bool BUF = CPT == 2;
+    constexpr bool BUF = F::G == 64 && F::ROUNDS == 2;
 
     // window slot j of output p holds gy[p - (TP-1) + j], tap t = TP-1-j
     float hp[TP][CPT];
