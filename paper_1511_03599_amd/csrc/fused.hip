@@ -98,10 +98,9 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_fwd_kernel(FusedArgs
     // waits only for the row that enters the window; other chunks test each
     // row. (Raw rows of a tile always lie inside the stream.)
     enum { TAIL = 0, FULL = 1, LAST = 2 };
-    // the untested chunk form needs registers the 16-tap, two-channel
-    // window does not leave (it spills, and every reload waits for all
-    // memory operations): that variant tests each row
-    constexpr bool EXACT = !(TP >= 16 && CPT == 2);
+    // The complex64 16-tap, two-channel variant keeps the tested form: with
+    // the untested forms it fits its registers but measures slower.
+    constexpr bool EXACT = !(DT == DT_C64 && TP >= 16 && CPT == 2);
     auto fir_chunk = [&](int base, auto kindc) PFB_INLINE {
         constexpr int KIND = decltype(kindc)::value;
         // raw row prefetched by row jj = 0 of this chunk
@@ -139,8 +138,13 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_fwd_kernel(FusedArgs
             const bool valid = ALL || base + r < nout;
             float2 *row = lds + r * S::PADDED;
             float2 *out = Yb + (int64_t)(base + r) * C;
+            // opaque lane index: the transform's LDS addresses are formed in
+            // each round instead of being hoisted out of the chunk loop and
+            // held in registers throughout
+            int ln = lane;
+            asm volatile("" : "+v"(ln));
             fft_run<LOG2C, G, false, true>(
-                lane, row, a.tw, [&](int idx) { return row[S::pad(idx)]; },
+                ln, row, a.tw, [&](int idx) { return row[S::pad(idx)]; },
                 [&](int idx, float2 v) {
                     if (valid)
                         store_nt(out + idx, v);
