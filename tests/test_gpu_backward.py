@@ -30,7 +30,9 @@ def adjoint_kind_cache(tmp_path, monkeypatch, C, T, S, B, ws):
 @pytest.mark.parametrize("C,T,S,B", [(32, 4, 20, 2), (256, 8, 100, 2), (1024, 16, 80, 3), (4096, 5, 10, 1),
                                      (64, 64, 100, 1), (1024, 33, 70, 1), (512, 1, 40, 2), (128, 16, 600, 1),
                                      (1024, 16, 700, 2), (256, 3, 530, 1), (512, 13, 257, 2),
-                                     (384, 8, 50, 2), (3072, 4, 12, 1), (105, 16, 40, 1)])
+                                     (384, 8, 50, 2), (3072, 4, 12, 1), (105, 16, 40, 1),
+                                     (1024, 7, 300, 2), (1024, 2, 45, 1), (1024, 16, 1, 1), (1024, 4, 3, 2),
+                                     (512, 16, 1000, 1), (512, 5, 17, 3)])
 @pytest.mark.parametrize("mode", ["default", "split", "single_role", "wave_specialised"])
 def test_backward_parity(dev, C, T, S, B, mode, tmp_path, monkeypatch):
     import torch
@@ -56,9 +58,10 @@ def test_backward_parity(dev, C, T, S, B, mode, tmp_path, monkeypatch):
     assert rel_l2(gh.cpu().numpy().astype(np.float64), gh_r) <= GH_TOL
 
 
-def test_backward_only_one_output(dev):
+@pytest.mark.parametrize("C,T,S", [(256, 8, 50), (512, 16, 70), (1024, 16, 90), (1024, 3, 40)])
+def test_backward_only_one_output(dev, C, T, S):
     pfb = pfbmod()
-    C, T, S = 256, 8, 50
+    say(f"backward one output C={C} T={T} S={S}")
     x = synth.quantise(synth.complex_gaussian((1, S + T - 1, C), 710), "c64")
     h = synth.random_taps(C, T, 711)
     gY = synth.quantise(synth.complex_gaussian((1, S, C), 712), "c64")
