@@ -49,6 +49,8 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_bwd_kernel(BwdArgs a
     constexpr int D = F::D;
     constexpr int G = F::G;
     __shared__ float2 lds[RB * S::PADDED];
+    // the interleaved form (below) reads its twiddles from LDS
+    __shared__ float2 tws[(F::G == 64 && F::ROUNDS == 2) ? fft_tw_entries<LOG2C>() : 1];
 
     const int tile = (int)(blockIdx.x % a.n_tiles);
     const int b = (int)(blockIdx.x / a.n_tiles);
@@ -214,6 +216,10 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_bwd_kernel(BwdArgs a
                 lds[(HALF + decltype(r)::value) * S::PADDED + S::pad(c0 + k)] = make_float2(0.0f, 0.0f);
             });
         });
+        // Twiddles from LDS: a wait for a global twiddle load would also
+        // wait for the x loads and gx stores of the gradient rows before it.
+        stage_twiddles_lds<LOG2C>(tws, a.tw, t, F::NT);
+        lds_barrier();
         gather_buf(gw);
         for (int base = 0; base < nq; base += RB) {
             sfor<2>([&](auto hc) PFB_INLINE {
@@ -226,8 +232,8 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_bwd_kernel(BwdArgs a
                 // loop and held in registers for both rounds
                 int ln = lane;
                 asm volatile("" : "+v"(ln));
-                fft_passes<LOG2C, G, true, false>(ln, row, a.tw, cur,
-                                                  [&](int idx, float2 v) { row[S::pad(idx)] = v; });
+                fft_passes<LOG2C, G, true, false, true>(ln, row, tws, cur,
+                                                        [&](int idx, float2 v) { row[S::pad(idx)] = v; });
                 lds_barrier();
                 // window slots holding rows of the half this round did not
                 // overwrite (the last min(TP, HALF) rows of that half)

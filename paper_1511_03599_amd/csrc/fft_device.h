@@ -171,21 +171,35 @@ __device__ __forceinline__ void fft_gather_first(int lane, Src &&src, float2 (&v
 // fft_gather_first); `dst(idx, v)` receives output element idx from the last
 // pass. When SRC_IN_LDS the inputs were read from this group's own LDS row,
 // so a multi-wave group synchronises before overwriting it.
-template <int LOG2C, int G, bool INV, bool SRC_IN_LDS, class Dst>
+//
+// TW_LDS: `tw` points to an LDS copy of the table laid out [pass][i][k]
+// (stage_twiddles_lds), so that the lanes of a butterfly column read
+// consecutive entries; LDS reads are counted apart from the caller's global
+// loads and stores, whereas a wait for a global twiddle load also waits for
+// every load and store issued before it.
+template <int LOG2C, int G, bool INV, bool SRC_IN_LDS, bool TW_LDS = false, class Dst>
 __device__ __forceinline__ void fft_passes(int lane, float2 *lds, const float2 *__restrict__ tw,
                                            float2 (&v)[FftShape<LOG2C, G>::E], Dst &&dst)
 {
     using S = FftShape<LOG2C, G>;
     constexpr int C = S::C;
     constexpr int E = S::E;
-    // Opaque copy of the twiddle pointer: keeps the compiler from hoisting
-    // the twiddle loads of every pass out of a caller's loop over rows, which
-    // would hold them all in registers at once. The copy is rebuilt as a
-    // global pointer: the opaque value has lost its address space, and flat
-    // loads would also count against the LDS counter.
-    const float2 *twp_opaque = tw;
-    asm volatile("" : "+v"(twp_opaque));
-    const float2 *twp = as_global(twp_opaque);
+    // Opaque twiddle address: keeps the compiler from hoisting the twiddle
+    // loads of every pass out of a caller's loop over rows, which would hold
+    // them all in registers at once. For an LDS table only an offset is
+    // opaque, so the pointer keeps its LDS origin; a global one is rebuilt as
+    // a global pointer (the opaque value has lost its address space, and
+    // flat loads would also count against the LDS counter).
+    const float2 *twp;
+    if constexpr (TW_LDS) {
+        int z = 0;
+        asm volatile("" : "+v"(z));
+        twp = tw + z;
+    } else {
+        const float2 *twp_opaque = tw;
+        asm volatile("" : "+v"(twp_opaque));
+        twp = as_global(twp_opaque);
+    }
 
     sfor<S::NPASS>([&](auto pp) PFB_INLINE {
         constexpr int P = decltype(pp)::value;
@@ -213,7 +227,14 @@ __device__ __forceinline__ void fft_passes(int lane, float2 *lds, const float2 *
         sfor<NB>([&](auto q) PFB_INLINE {
             constexpr int Q = decltype(q)::value;
             const int j = lane + G * Q;
-            if constexpr (L > 1) {
+            if constexpr (L > 1 && TW_LDS) {
+                const int k = j & (L - 1);
+                constexpr int PO = S::pass_offset(P);
+                sfor<R - 1>([&](auto ic) PFB_INLINE {
+                    constexpr int i = decltype(ic)::value + 1;
+                    v[Q * R + i] = cmul(v[Q * R + i], twp[PO + i * L + k]);
+                });
+            } else if constexpr (L > 1) {
                 const int k = j & (L - 1);
                 constexpr int PO = S::pass_offset(P);
                 const float4 *wp = reinterpret_cast<const float4 *>(twp + PO + k * R);
@@ -264,6 +285,29 @@ __device__ __forceinline__ void fft_run(int lane, float2 *lds, const float2 *__r
     float2 v[FftShape<LOG2C, G>::E];
     fft_gather_first<LOG2C, G, INV>(lane, src, v);
     fft_passes<LOG2C, G, INV, SRC_IN_LDS>(lane, lds, tw, v, dst);
+}
+
+// Entries of a C = 2^LOG2C point transform's twiddle table (at least 1, for
+// array sizes).
+template <int LOG2C> constexpr int fft_tw_entries()
+{
+    return FftSchedule(LOG2C).table_size() > 0 ? FftSchedule(LOG2C).table_size() : 1;
+}
+
+// Copy the twiddle table (global layout [pass][k][i]) into LDS as
+// [pass][i][k], thread t of nt; a workgroup barrier must follow before the
+// first transform reads it.
+template <int LOG2C> __device__ __forceinline__ void stage_twiddles_lds(float2 *dst, const float2 *tw, int t, int nt)
+{
+    constexpr FftSchedule SC{LOG2C};
+    sfor<SC.npass>([&](auto pp) PFB_INLINE {
+        constexpr int P = decltype(pp)::value;
+        if constexpr (P > 0) {
+            constexpr int R = SC.radix(P), L = SC.stride(P), PO = SC.pass_offset(P);
+            for (int e = t; e < R * L; e += nt)
+                dst[PO + (e % R) * L + e / R] = tw[PO + e];
+        }
+    });
 }
 
 // Lanes per transform: C <= 1024 lives in one wave (or part of one); larger C
