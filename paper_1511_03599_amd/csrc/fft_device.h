@@ -278,13 +278,13 @@ __device__ __forceinline__ void fft_passes(int lane, float2 *lds, const float2 *
 // Run one transform. `src(idx)` returns input element idx (first pass);
 // `dst(idx, v)` receives output element idx (last pass). When SRC_IN_LDS the
 // first pass reads this group's own LDS row. INV selects exp(+...).
-template <int LOG2C, int G, bool INV, bool SRC_IN_LDS, class Src, class Dst>
+template <int LOG2C, int G, bool INV, bool SRC_IN_LDS, bool TW_LDS = false, class Src, class Dst>
 __device__ __forceinline__ void fft_run(int lane, float2 *lds, const float2 *__restrict__ tw, Src &&src,
                                         Dst &&dst)
 {
     float2 v[FftShape<LOG2C, G>::E];
     fft_gather_first<LOG2C, G, INV>(lane, src, v);
-    fft_passes<LOG2C, G, INV, SRC_IN_LDS>(lane, lds, tw, v, dst);
+    fft_passes<LOG2C, G, INV, SRC_IN_LDS, TW_LDS>(lane, lds, tw, v, dst);
 }
 
 // Entries of a C = 2^LOG2C point transform's twiddle table (at least 1, for

@@ -48,6 +48,9 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_fwd_kernel(FusedArgs
     constexpr int D = F::D;
     constexpr int G = F::G;
     __shared__ float2 lds[RB * S::PADDED];
+    // twiddles read from LDS: a wait for a global twiddle load would also
+    // wait for the raw rows prefetched before it
+    __shared__ float2 tws[fft_tw_entries<LOG2C>()];
 
     const int64_t lb = blockIdx.x;
     const int tile = (int)(lb % a.n_tiles);
@@ -59,6 +62,8 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_fwd_kernel(FusedArgs
     const int off = TP - a.T;
     const int64_t row0 = s_begin - off;
     const int64_t in_rows = a.S + a.T - 1;
+
+    stage_twiddles_lds<LOG2C>(tws, a.tw, t, F::NT); // read after the first chunk's barrier
 
     float hp[TP][CPT];
 #pragma unroll
@@ -143,8 +148,8 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_fwd_kernel(FusedArgs
             // held in registers throughout
             int ln = lane;
             asm volatile("" : "+v"(ln));
-            fft_run<LOG2C, G, false, true>(
-                ln, row, a.tw, [&](int idx) { return row[S::pad(idx)]; },
+            fft_run<LOG2C, G, false, true, true>(
+                ln, row, tws, [&](int idx) { return row[S::pad(idx)]; },
                 [&](int idx, float2 v) {
                     if (valid)
                         store_nt(out + idx, v);
