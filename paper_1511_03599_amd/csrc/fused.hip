@@ -103,9 +103,6 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_fwd_kernel(FusedArgs
     // waits only for the row that enters the window; other chunks test each
     // row. (Raw rows of a tile always lie inside the stream.)
     enum { TAIL = 0, FULL = 1, LAST = 2 };
-    // The complex64 16-tap, two-channel variant keeps the tested form: with
-    // the untested forms it fits its registers but measures slower.
-    constexpr bool EXACT = !(DT == DT_C64 && TP >= 16 && CPT == 2);
     auto fir_chunk = [&](int base, auto kindc) PFB_INLINE {
         constexpr int KIND = decltype(kindc)::value;
         // raw row prefetched by row jj = 0 of this chunk
@@ -157,48 +154,19 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_fwd_kernel(FusedArgs
         }
     };
 
-    if constexpr (EXACT) {
-        for (int base = 0; base < nout; base += RB) {
-            if (base + RB + D <= nout)
-                fir_chunk(base, std::integral_constant<int, FULL>{});
-            else if (base + RB == nout)
-                fir_chunk(base, std::integral_constant<int, LAST>{});
-            else
-                fir_chunk(base, std::integral_constant<int, TAIL>{});
-            lds_barrier();
-            if (base + RB <= nout)
-                fft_chunk(base, std::true_type{});
-            else
-                fft_chunk(base, std::false_type{});
-            lds_barrier();
-        }
-    } else {
-        for (int base = 0; base < nout; base += RB) {
-            // 1. FIR into the LDS row buffer
-#pragma unroll
-            for (int jj = 0; jj < RB; ++jj) {
-                const int o = base + jj;
-                if (o < nout) {
-                    unpack<DT, CPT>(pf[jj % D], w[(jj + TP - 1) % TP]);
-                    if (o + D < nout)
-                        ldp(row0 + o + D + TP - 1, pf[jj % D]);
-#pragma unroll
-                    for (int k = 0; k < CPT; ++k) {
-                        float ar = 0.0f, ai = 0.0f;
-#pragma unroll
-                        for (int j = 0; j < TP; ++j) {
-                            ar = __builtin_fmaf(hp[j][k], w[(jj + j) % TP][k].x, ar);
-                            ai = __builtin_fmaf(hp[j][k], w[(jj + j) % TP][k].y, ai);
-                        }
-                        lds[jj * S::PADDED + S::pad(c0 + k)] = make_float2(ar, ai);
-                    }
-                }
-            }
-            lds_barrier();
-            // 2. FFT of the chunk's rows, straight to HBM
+    for (int base = 0; base < nout; base += RB) {
+        if (base + RB + D <= nout)
+            fir_chunk(base, std::integral_constant<int, FULL>{});
+        else if (base + RB == nout)
+            fir_chunk(base, std::integral_constant<int, LAST>{});
+        else
+            fir_chunk(base, std::integral_constant<int, TAIL>{});
+        lds_barrier();
+        if (base + RB <= nout)
+            fft_chunk(base, std::true_type{});
+        else
             fft_chunk(base, std::false_type{});
-            lds_barrier();
-        }
+        lds_barrier();
     }
 }
 
