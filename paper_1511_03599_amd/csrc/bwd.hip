@@ -50,7 +50,9 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_bwd_kernel(BwdArgs a
     constexpr int G = F::G;
     __shared__ float2 lds[RB * S::PADDED];
     // the interleaved form (below) reads its twiddles from LDS
-    __shared__ float2 tws[(F::G == 64 && F::ROUNDS == 2) ? fft_tw_entries<LOG2C>() : 1];
+    // twiddles read from LDS: a wait for a global twiddle load would also
+    // wait for the x loads and gx stores issued before it
+    __shared__ float2 tws[fft_tw_entries<LOG2C>()];
 
     const int tile = (int)(blockIdx.x % a.n_tiles);
     const int b = (int)(blockIdx.x / a.n_tiles);
@@ -66,11 +68,10 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_bwd_kernel(BwdArgs a
     const bool want_gh = a.part != nullptr;
     const bool both = want_gx && want_gh;
     enum { TAIL = 0, FULL = 1, LAST = 2 };
-    // the untested chunk form needs registers the 16-tap, two-channel
-    // window does not leave (it spills, and every reload waits for all
-    // memory operations): that variant runs every row unconditionally
-    // through bounded views instead (BUF below)
-    constexpr bool EXACT = !(TP >= 16 && CPT == 2);
+    // BUF: one wave per transform and two transform rounds per chunk
+    // (C=512, C=1024): every row runs unconditionally through bounded
+    // views, and the rounds interleave with the gradient rows (below);
+    // otherwise the chunk forms FULL and TAIL
     constexpr bool BUF = F::G == 64 && F::ROUNDS == 2;
 
     // window slot j of output p holds gy[p - (TP-1) + j], tap t = TP-1-j
@@ -216,8 +217,6 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_bwd_kernel(BwdArgs a
                 lds[(HALF + decltype(r)::value) * S::PADDED + S::pad(c0 + k)] = make_float2(0.0f, 0.0f);
             });
         });
-        // Twiddles from LDS: a wait for a global twiddle load would also
-        // wait for the x loads and gx stores of the gradient rows before it.
         stage_twiddles_lds<LOG2C>(tws, a.tw, t, F::NT);
         lds_barrier();
         gather_buf(gw);
@@ -250,6 +249,8 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_bwd_kernel(BwdArgs a
             });
         }
     } else {
+    stage_twiddles_lds<LOG2C>(tws, a.tw, t, F::NT);
+    lds_barrier();
     if constexpr (AHEAD)
         gather(0, 0);
     for (int base = 0; base < nq; base += RB) {
@@ -268,8 +269,8 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_bwd_kernel(BwdArgs a
                 sfor<E>([&](auto e) PFB_INLINE { cur[e] = gv[e]; });
             }
             float2 *row = lds + (round * F::NG + gid) * S::PADDED;
-            fft_passes<LOG2C, G, true, false>(lane, row, a.tw, cur,
-                                              [&](int idx, float2 v) { row[S::pad(idx)] = v; });
+            fft_passes<LOG2C, G, true, false, true>(lane, row, tws, cur,
+                                                    [&](int idx, float2 v) { row[S::pad(idx)] = v; });
         }
         lds_barrier();
         // 2. sample gradient and tap-gradient partials. In FULL chunks (every
