@@ -8,10 +8,13 @@ gcc and OpenMP), and this module only marshals numpy arrays into it.
 Functions and the passages they follow:
   fir            -- Sec. 3.2, Algorithm 1 (the FIR of Sec. 2, first step)
   dft            -- Sec. 2, Eq. (2); sign=+1 gives the unnormalised inverse
+  dft_bins       -- Eq. (2) evaluated at listed output indices only
   pfb_forward    -- Sec. 2 two-step scheme: FIR, then DFT of each spectrum
   fir_adjoint_x  -- adjoint of Algorithm 1 in the samples
   fir_adjoint_h  -- adjoint of Algorithm 1 in the coefficients
   pfb_adjoint    -- adjoint of the two-step scheme (inverse DFT, then both)
+  pfb_adjoint_h_channels -- its tap gradient at listed channels only
+  pfb_adjoint_x_rows     -- its sample gradient at listed raw spectra only
   leakage_loss   -- out-of-channel power of the frequency spectra and its
                     gradient (a training objective built on the scheme)
 """
@@ -54,9 +57,12 @@ def _load():
     lib.oracle_fir_adjoint_x.argtypes = [P, P, I, I, I, I, P]
     lib.oracle_fir_adjoint_h.argtypes = [P, P, I, I, I, I, P]
     lib.oracle_pfb_adjoint.argtypes = [P, P, P, I, I, I, I, P, P]
+    lib.oracle_dft_bins.argtypes = [P, I, I, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), I, P]
     lib.oracle_num_threads.argtypes = []
-    for f in ("oracle_fir", "oracle_dft", "oracle_pfb_forward", "oracle_fir_adjoint_x",
-              "oracle_fir_adjoint_h", "oracle_pfb_adjoint", "oracle_num_threads"):
+    lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+    for f in ("oracle_fir", "oracle_dft", "oracle_dft_bins", "oracle_pfb_forward", "oracle_fir_adjoint_x",
+              "oracle_fir_adjoint_h", "oracle_pfb_adjoint", "oracle_num_threads",
+              "oracle_set_num_threads"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -64,6 +70,11 @@ def _load():
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads for the following oracle calls from this thread."""
+    _check(_load().oracle_set_num_threads(int(n)), "oracle_set_num_threads")
 
 
 def _as_c128(a) -> np.ndarray:
@@ -121,6 +132,21 @@ def dft(a, sign: int = -1) -> np.ndarray:
     return out
 
 
+def dft_bins(a, bins, sign: int = -1) -> np.ndarray:
+    """Eq. (2) along the last axis, evaluated only at the output indices
+    `bins` (the plain definition at those indices). Returns complex128 of
+    shape a.shape[:-1] + (len(bins),)."""
+    a = _as_c128(a)
+    C = a.shape[-1]
+    b = np.ascontiguousarray(np.asarray(bins, dtype=np.int64))
+    nrows = a.size // C if C else 0
+    out = np.empty(a.shape[:-1] + (b.size,), dtype=np.complex128)
+    _check(_load().oracle_dft_bins(_ptr(a), nrows, C, int(sign),
+                                   b.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), b.size, _ptr(out)),
+           "oracle_dft_bins")
+    return out
+
+
 def pfb_forward(x, h, want_y: bool = False):
     """Frequency spectra Y[B, S, C]; with want_y also the filtered spectra."""
     x, h, B, S, C, T = _shape_fir(x, h)
@@ -172,6 +198,42 @@ def pfb_adjoint(x, h, gY):
     _check(_load().oracle_pfb_adjoint(_ptr(x), _ptr(h), _ptr(gY), B, S, C, T, _ptr(gx),
                                       _ptr(gh)), "oracle_pfb_adjoint")
     return gx, gh
+
+
+def pfb_adjoint_h_channels(x, gY, T: int, channels) -> np.ndarray:
+    """Tap gradient of the adjoint (as pfb_adjoint) at the listed channels
+    only: gh[t, j] for channel channels[j], shape [T, len(channels)].
+    The filtered-spectra gradient of channel c is the inverse DFT of gY
+    (adjoint of Eq. (2)) evaluated at output index c, and the tap gradient of
+    channel c depends on that channel alone (adjoint of Algorithm 1), so
+    both steps restrict exactly to the listed channels."""
+    ch = np.asarray(channels, dtype=np.int64)
+    gy = dft_bins(gY, ch, +1)
+    x = np.asarray(x)
+    xs = x[:, :, ch] if np.iscomplexobj(x) else x[:, :, ch, :]
+    return fir_adjoint_h(gy, xs, T)
+
+
+def pfb_adjoint_x_rows(h, gY, rows) -> np.ndarray:
+    """Sample gradient of the adjoint (as pfb_adjoint) at the listed raw
+    spectra p only, shape [B, len(rows), C]. gx[p] depends on the filtered
+    gradient rows p-T+1 .. p inside [0, S) (adjoint of Algorithm 1), each the
+    inverse DFT of one gY row (adjoint of Eq. (2)); those rows alone are
+    transformed and scattered back."""
+    gY = _as_c128(gY)
+    if gY.ndim == 2:
+        gY = gY[None]
+    h = np.ascontiguousarray(np.asarray(h), dtype=np.float64)
+    B, S, C = gY.shape
+    T = h.shape[0]
+    out = np.empty((B, len(rows), C), dtype=np.complex128)
+    for j, p in enumerate(rows):
+        if not 0 <= p < S + T - 1:
+            raise ValueError(f"row {p} outside [0, S+T-1)")
+        s0, s1 = max(0, p - T + 1), min(S, p + 1)
+        gy = dft(gY[:, s0:s1], +1)
+        out[:, j] = fir_adjoint_x(gy, h)[:, p - s0]
+    return out
 
 
 def leakage_loss(Y, tone_bins):

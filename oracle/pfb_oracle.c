@@ -52,6 +52,17 @@ int oracle_num_threads(void)
 #endif
 }
 
+/* Threads used by the following calls from this host thread (n >= 1). */
+int oracle_set_num_threads(int n)
+{
+    if (n < 1)
+        return ORACLE_EINVAL;
+#ifdef _OPENMP
+    omp_set_num_threads(n);
+#endif
+    return ORACLE_OK;
+}
+
 /*
  * FIR step (Sec. 2, first step of the scheme; Sec. 3.2, Algorithm 1).
  *   y[b][s][c] = sum_{t=0}^{T-1} h[t*C + c] * x[b][s+t][c]
@@ -131,6 +142,46 @@ int oracle_dft(const double *in, int64_t nrows, int64_t C, int sign, double *out
             }
             RE(dst, m) = acc_re;
             IM(dst, m) = acc_im;
+        }
+    }
+    free(w);
+    return ORACLE_OK;
+}
+
+/*
+ * The same DFT (Sec. 2, Eq. (2)) evaluated only at the listed output indices:
+ *   out[r][j] = sum_{n=0}^{C-1} in[r][n] * exp(sign * 2 pi i n bins[j] / C)
+ * for every row r and j < nbins (each bins[j] in [0, C)). This is the plain
+ * definition at fewer indices, so a few bins of a very long set of rows cost
+ * O(rows * C * nbins) instead of O(rows * C^2). out: [nrows][nbins] complex.
+ */
+int oracle_dft_bins(const double *in, int64_t nrows, int64_t C, int sign,
+                    const int64_t *bins, int64_t nbins, double *out)
+{
+    if (nrows < 0 || C < 1 || nbins < 0 || !in || !out || (nbins > 0 && !bins) ||
+        (sign != 1 && sign != -1))
+        return ORACLE_EINVAL;
+    for (int64_t j = 0; j < nbins; ++j)
+        if (bins[j] < 0 || bins[j] >= C)
+            return ORACLE_EINVAL;
+    double *w = twiddles(C, sign);
+    if (!w)
+        return ORACLE_ENOMEM;
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < nrows; ++r) {
+        const double *row = in + 2 * r * C;
+        for (int64_t j = 0; j < nbins; ++j) {
+            const int64_t m = bins[j];
+            double acc_re = 0.0, acc_im = 0.0;
+            for (int64_t n = 0; n < C; ++n) {
+                int64_t k = (n * m) % C;
+                double a = RE(row, n), bb = IM(row, n);
+                double wr = RE(w, k), wi = IM(w, k);
+                acc_re += a * wr - bb * wi;
+                acc_im += a * wi + bb * wr;
+            }
+            RE(out, r * nbins + j) = acc_re;
+            IM(out, r * nbins + j) = acc_im;
         }
     }
     free(w);

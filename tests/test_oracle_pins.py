@@ -216,6 +216,35 @@ def test_fir_adjoints_against_explicit_matrix():
     assert rel(gh, want_h) <= 1e-14
 
 
+@pytest.mark.parametrize("C", [8, 12, 64])
+def test_dft_at_listed_bins_matches_library_fft(C):
+    """Eq. (2) at a few output indices equals the library FFT at those bins;
+    the inverse sign equals C times the library inverse FFT there."""
+    a = synth.complex_gaussian((5, C), 81 + C)
+    bins = [0, C - 1, C // 2, 3, 3]
+    assert rel(oracle.dft_bins(a, bins), np.fft.fft(a, axis=-1)[:, bins]) <= 1e-13
+    assert rel(oracle.dft_bins(a, bins, +1), C * np.fft.ifft(a, axis=-1)[:, bins]) <= 1e-13
+
+
+def test_restricted_adjoints_equal_the_pinned_full_adjoint():
+    """The tap gradient at listed channels and the sample gradient at listed
+    raw spectra, as used at sizes where the full adjoint is too slow, equal
+    the corresponding entries of the full adjoint (itself pinned above by the
+    dot-product identities, the explicit matrix and finite differences),
+    including rows at both ends where fewer than T filtered rows contribute."""
+    B, S, C, T = 3, 11, 16, 5
+    x, h = rand_stream(B, S, C, T, 91)
+    gY = synth.complex_gaussian((B, S, C), 92)
+    gx, gh = oracle.pfb_adjoint(x, h, gY)
+    ch = [0, 15, 7, 7, 3]
+    assert rel(oracle.pfb_adjoint_h_channels(x, gY, T, ch), gh[:, ch]) <= 1e-13
+    xs = synth.quantise(x, "c64")      # the stored (..., 2) form is accepted too
+    gh32 = oracle.pfb_adjoint(xs, h, gY)[1]
+    assert rel(oracle.pfb_adjoint_h_channels(xs, gY, T, ch), gh32[:, ch]) <= 1e-13
+    rows = [0, 1, T - 1, S - 1, S, S + T - 2]
+    assert rel(oracle.pfb_adjoint_x_rows(h, gY, rows), gx[:, rows]) <= 1e-13
+
+
 def test_leakage_loss_gradient_finite_difference_small():
     """Central differences (step 1e-6) of the out-of-channel loss against the
     oracle adjoint, on every tap and on a set of samples. The loss is quadratic
