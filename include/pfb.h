@@ -123,6 +123,8 @@ typedef struct {
                               wave-specialised form (same results)          */
     int32_t fused_ws;      /* 1 if the fused forward runs its wave-specialised
                               form (same results as the single-role kernel)  */
+    int32_t backward_rows; /* sample-gradient rows per adjoint tile (fused
+                              adjoint) or per adjoint FIR tile (split)      */
 } pfb_plan_info;
 
 /*

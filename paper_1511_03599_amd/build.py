@@ -1,10 +1,12 @@
 """Build the HIP library libpfb.so for gfx950 (in-tree, next to this file).
 
-    python -m paper_1511_03599_amd.build [--jobs N]
+    python -m paper_1511_03599_amd.build [--jobs N] [--changed]
 
 Every source under csrc/ is compiled by hipcc to an object in _build/, then
-linked into libpfb.so. The build always recompiles (it is the "does it build"
-check as well as the build).
+linked into libpfb.so. By default the build recompiles everything (it is the
+"does it build" check as well as the build); --changed recompiles only the
+sources whose object is older than the source or than any header in csrc/
+or include/.
 """
 from __future__ import annotations
 
@@ -46,7 +48,7 @@ def sources() -> list[str]:
 
 
 def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    obj = _obj(src)
     cmd = [hipcc(), *HIP_FLAGS, "-c", src, "-o", obj]
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     out = "\n".join(l for l in r.stdout.splitlines() if "packed-fp32-ops" not in l)
@@ -57,12 +59,27 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
+def _obj(src: str) -> str:
+    return os.path.join(BUILD, os.path.basename(src) + ".o")
+
+
+def _stale(src: str) -> bool:
+    obj = _obj(src)
+    if not os.path.exists(obj):
+        return True
+    headers = glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(HERE, "..", "include", "*.h"))
+    newest = max([os.path.getmtime(src)] + [os.path.getmtime(h) for h in headers])
+    return os.path.getmtime(obj) < newest
+
+
+def build(jobs: int | None = None, verbose: bool = False, changed_only: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
-    jobs = jobs or min(len(srcs), max(1, os.cpu_count() or 1))
+    todo = [s for s in srcs if _stale(s)] if changed_only else srcs
+    jobs = jobs or min(max(1, len(todo)), max(1, os.cpu_count() or 1))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        list(ex.map(_compile, todo))
+    objs = [_obj(s) for s in srcs]
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
@@ -77,8 +94,9 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=None)
+    ap.add_argument("--changed", action="store_true", help="recompile only out-of-date sources")
     args = ap.parse_args()
-    build(args.jobs, verbose=True)
+    build(args.jobs, verbose=True, changed_only=args.changed)
 
 
 if __name__ == "__main__":

@@ -471,6 +471,7 @@ extern "C" pfb_status pfb_plan_get_info(const pfb_plan *p, pfb_plan_info *info)
     info->backward_fused = p->bwd_fused ? (p->bwd_ws ? 2 : 1) : 0;
     info->fused_ws = (p->path == PATH_FUSED && p->fused_ws) ? 1 : 0;
     info->chunk_rows = p->chunk_rows;
+    info->backward_rows = p->bwd_fused ? p->bwd_sb : p->fir_sb;
     return PFB_OK;
 }
 

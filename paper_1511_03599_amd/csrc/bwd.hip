@@ -146,8 +146,10 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_bwd_kernel(BwdArgs a
         // Each round's gY loads are issued GAT gradient rows before the round
         // starts (into gv, which the gradient rows leave room for), so their
         // latency hides behind those rows. A round writes LDS rows that no
-        // wave reads until the barrier after it, and the rows it overwrites
-        // were last read before the previous barrier, so one barrier per
+        // wave reads until the barrier after it; the rows it overwrites were
+        // last read (by the gradient rows and by the read-back of the other
+        // half, both of which every wave finishes before it reaches the
+        // previous barrier) before the previous barrier, so one barrier per
         // round suffices.
         static_assert(F::ROUNDS == 2 && F::NG * 2 == RB, "two transform rounds per chunk");
         constexpr int HALF = RB / 2;
@@ -233,14 +235,19 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_bwd_kernel(BwdArgs a
                 asm volatile("" : "+v"(ln));
                 fft_passes<LOG2C, G, true, false, true>(ln, row, tws, cur,
                                                         [&](int idx, float2 v) { row[S::pad(idx)] = v; });
-                lds_barrier();
                 // window slots holding rows of the half this round did not
-                // overwrite (the last min(TP, HALF) rows of that half)
+                // overwrite (the last min(TP, HALF) rows of that half). They
+                // are read back before this round's barrier: those rows were
+                // written before the previous barrier, and the next round,
+                // which overwrites them, starts only after this barrier, so
+                // no wave can overwrite a row that another wave is still
+                // reading back.
                 constexpr int NRR = TP < HALF ? TP : HALF;
                 sfor<NRR>([&](auto rc) PFB_INLINE {
                     constexpr int r = (1 - H) * HALF + HALF - NRR + decltype(rc)::value;
                     sfor<CPT>([&](auto k) PFB_INLINE { w[r % TP][k] = lds[r * S::PADDED + S::pad(c0 + k)]; });
                 });
+                lds_barrier();
                 sfor<HALF>([&](auto jc) PFB_INLINE {
                     grad_row(base, std::integral_constant<int, H * HALF + decltype(jc)::value>{});
                     if constexpr (decltype(jc)::value == (H == 0 ? GAT0 : GAT1))

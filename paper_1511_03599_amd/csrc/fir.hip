@@ -19,22 +19,9 @@
 // Rows outside [0, in_rows) read as zero. The same kernel computes the
 // adjoint in the samples (REV: taps reversed, shift = off + T - 1), which is
 // the "full" correlation of the filtered-spectra gradient with the taps.
-#include "fir_device.h"
-#include "launch.h"
+#include "fir_launch.h"
 
 namespace pfb {
-
-template <int DT, int TP, int CPT, int D, bool REV>
-__global__ __launch_bounds__(256, 2) void fir_kernel(FirArgs a)
-{
-    // Consecutive waves take consecutive channel chunks, then consecutive
-    // tiles, so the waves resident at any time sweep one narrow band of rows.
-    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave_id();
-    const int64_t total = (int64_t)a.B * a.n_tiles * a.n_cchunks;
-    if (gw >= total)
-        return;
-    fir_wave_task<DT, TP, CPT, D, REV>(a, gw);
-}
 
 // Tap gradient, first stage: per tile of filtered spectra and per channel,
 //   part[tile][t][c] = sum_{s in tile} Re(conj(gy[s][c]) x[s+t][c])
@@ -104,8 +91,11 @@ __global__ __launch_bounds__(256) void gh_partial_kernel(GhArgs a)
     }
 }
 
-// Tap gradient, second stage: gh[t][c] = sum over all tiles of the partials,
-// in ascending tile order (a fixed order, so the result is reproducible).
+// Tap gradient, second stage: gh[t][c] = sum over all tiles of the partials.
+// Tile p goes to running sum p mod 4 (each sum takes its tiles in ascending
+// order, the tail tiles beyond a multiple of four go to the first one), and
+// the four sums are combined as (s0 + s1) + (s2 + s3): a fixed order, so the
+// result is bit-reproducible.
 __global__ __launch_bounds__(256) void gh_reduce_kernel(const float *__restrict__ part, float *__restrict__ gh,
                                                         int64_t n_parts, int64_t tc)
 {
@@ -129,53 +119,19 @@ __global__ __launch_bounds__(256) void gh_reduce_kernel(const float *__restrict_
 // Host launchers
 // ----------------------------------------------------------------------------
 
-template <int DT, int TP, int CPT, bool REV>
-static hipError_t launch_fir_t(const FirArgs &a, hipStream_t st)
-{
-    constexpr int D = fir_prefetch(TP);
-    const int64_t total = (int64_t)a.B * a.n_tiles * a.n_cchunks;
-    const int64_t blocks = (total + 3) / 4;
-    if (blocks <= 0)
-        return hipSuccess;
-    hipLaunchKernelGGL((fir_kernel<DT, TP, CPT, D, REV>), dim3((unsigned)blocks), dim3(256), 0, st, a);
-    return hipGetLastError();
-}
-
-template <int DT, bool REV>
-static hipError_t launch_fir_dt(const FirArgs &a, int tp, int cpt, hipStream_t st)
-{
-#define PFB_FIR_CASE(TPV)                                                                                    \
-    case TPV:                                                                                                \
-        return cpt == 2 ? launch_fir_t<DT, TPV, 2, REV>(a, st) : launch_fir_t<DT, TPV, 1, REV>(a, st);
-    // two channels per lane only where the doubled window still fits in
-    // registers; the larger windows run one channel per lane
-    switch (tp) {
-        PFB_FIR_CASE(4)
-        PFB_FIR_CASE(8)
-        PFB_FIR_CASE(16)
-    case 32:
-        return launch_fir_t<DT, 32, 1, REV>(a, st);
-    case 64:
-        return launch_fir_t<DT, 64, 1, REV>(a, st);
-    default:
-        return hipErrorInvalidValue;
-    }
-#undef PFB_FIR_CASE
-}
-
 hipError_t launch_fir(const FirArgs &a, int dtype, int tp, int cpt, bool rev, hipStream_t st)
 {
     if (rev)
-        return dtype == DT_C64 ? launch_fir_dt<DT_C64, true>(a, tp, cpt, st) : hipErrorInvalidValue;
+        return dtype == DT_C64 ? launch_fir_adjoint(a, tp, cpt, st) : hipErrorInvalidValue;
     switch (dtype) {
     case DT_C64:
         return launch_fir_dt<DT_C64, false>(a, tp, cpt, st);
     case DT_CI16:
-        return launch_fir_dt<DT_CI16, false>(a, tp, cpt, st);
+        return launch_fir_ci16(a, tp, cpt, st);
     case DT_CI8:
-        return launch_fir_dt<DT_CI8, false>(a, tp, cpt, st);
+        return launch_fir_ci8(a, tp, cpt, st);
     case DT_CF16:
-        return launch_fir_dt<DT_CF16, false>(a, tp, cpt, st);
+        return launch_fir_cf16(a, tp, cpt, st);
     default:
         return hipErrorInvalidValue;
     }

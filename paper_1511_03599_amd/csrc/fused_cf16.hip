@@ -1,0 +1,11 @@
+// Fused FIR + FFT (fused_launch.h) for cf16 input.
+#include "fused_launch.h"
+
+namespace pfb {
+
+hipError_t launch_fused_cf16(const FusedArgs &a, int tp, int log2c, hipStream_t st)
+{
+    return launch_fused_dt<DT_CF16>(a, tp, log2c, st);
+}
+
+} // namespace pfb

@@ -73,6 +73,11 @@ struct BwdArgs {
 };
 
 hipError_t launch_fir(const FirArgs &a, int dtype, int tp, int cpt, bool rev, hipStream_t st);
+// per input type (each in its own translation unit)
+hipError_t launch_fir_ci16(const FirArgs &a, int tp, int cpt, hipStream_t st);
+hipError_t launch_fir_ci8(const FirArgs &a, int tp, int cpt, hipStream_t st);
+hipError_t launch_fir_cf16(const FirArgs &a, int tp, int cpt, hipStream_t st);
+hipError_t launch_fir_adjoint(const FirArgs &a, int tp, int cpt, hipStream_t st); // reversed taps, c64
 // FIR for T beyond the register window: tiles of 32 rows (SB = 32), one
 // channel per lane (64 per wave task), no tap padding (shift = 0).
 hipError_t launch_fir_long(const FirArgs &a, int dtype, hipStream_t st);
@@ -98,6 +103,10 @@ struct GfftSched {
 bool gfft_schedule(int C, GfftSched *s);
 hipError_t launch_gfft(const FftArgs &a, const GfftSched &s, bool inv, hipStream_t st);
 hipError_t launch_fused(const FusedArgs &a, int dtype, int tp, int log2c, hipStream_t st);
+// per input type (each in its own translation unit)
+hipError_t launch_fused_ci16(const FusedArgs &a, int tp, int log2c, hipStream_t st);
+hipError_t launch_fused_ci8(const FusedArgs &a, int tp, int log2c, hipStream_t st);
+hipError_t launch_fused_cf16(const FusedArgs &a, int tp, int log2c, hipStream_t st);
 hipError_t launch_fused_ws(const FusedArgs &a, int dtype, int tp, int log2c, hipStream_t st);
 // nblk blocks of `bytes` bytes from src + b*src_stride to dst + b*dst_stride
 // (src NULL: zeros).
