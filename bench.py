@@ -3,17 +3,19 @@
 One step = one pass of the whole hot path over one batch of synthetic input
 already resident in HBM: the forward filter bank (ingest + convert, FIR, FFT,
 write) followed by its adjoint (inverse FFT, sample gradient, tap gradient).
-Workload: one stream of 65536 filtered spectra, C = 1024 channels, T = 16
-taps, complex64 Gaussian noise input, Hamming-windowed sinc taps (the
-tap-sweep workload at the paper's default channel count, at 16 taps).
+Workload: the differentiable filter bank, 32 streams x 8192 filtered spectra,
+C = 1024 channels, T = 16 taps, complex64 off-centre tones, Hamming-windowed
+sinc taps, a seeded complex64 frequency-spectra gradient.
 
 Prints ONE JSON line. `value` is the real-time sample rate in Msamples/s
 (new input samples B*S*C per second of the fwd+bwd step). The same step on the
 plain comparator (unfused FIR launch then FFT launch, split adjoint) is timed
-beside it, and the oracle is timed on a bounded sample on the host cores.
+beside it, and the oracle is timed on bounded samples on the host cores.
 Unless --quick is given, `extras` adds the other workloads: the forward pass
-over T in {4..64}, the low-precision inputs, the 64-beam batched launch
-against 64 separate plain launches, and the 32-stream differentiable pass.
+over T in {4..64} at C=1024 (one stream of 65536 spectra, also timed fwd+bwd),
+the low-precision inputs at C=4096 with their errors against FP64, the
+64-beam batched launch against 64 separate plain launches, and the layouts
+of the later rows (streaming, non-power-of-two channel counts, sub-bands).
 
     python bench.py [--steps K] [--warmup W] [--no-cpu] [--quick]
 """
@@ -81,23 +83,74 @@ def time_calls(fn, n, stream):
     return start.elapsed_time(end) / n
 
 
-def cpu_baseline(C, T, rows_sample, seed):
-    """The oracle (plain FP64 C, OpenMP) on a bounded sample of the same
-    workload: forward and adjoint of `rows_sample` spectra of one stream."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(B, S, C, T, seed):
+    """The oracle (plain FP64 C, OpenMP) timed on bounded samples of the
+    step's workload, each part on its own: the FIR (Algorithm 1), the DFT
+    (Eq. (2), direct O(C^2) per spectrum), the inverse DFT of the gradient,
+    and the two FIR adjoints; once on all host threads and once on one.
+    Each part's time is scaled linearly from its sample to the whole step
+    (B*S spectra) -- the DFT parts are therefore extrapolated -- and `value`
+    is B*S*C over the sum, on all threads."""
     import oracle
     from paper_1511_03599_amd import synth
-    st = synth.noise_stream(1, C, T, rows_sample, seed)
-    g = synth.rng(seed + 1)
-    gY = (g.standard_normal((1, rows_sample, C)) + 1j * g.standard_normal((1, rows_sample, C)))
-    oracle.pfb_forward(st.x[:, :T + 1], st.h)  # load and warm the library
-    t0 = time.perf_counter()
-    oracle.pfb_forward(st.x, st.h)
-    oracle.pfb_adjoint(st.x, st.h, gY)
-    dt = time.perf_counter() - t0
-    return {"value": round(rows_sample * C / dt / 1e6, 3), "unit": "Msamples/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"forward + adjoint of {rows_sample} spectra of the C={C}, T={T} stream "
-                      f"(FP64 direct FIR and O(C^2) DFT): {dt:.1f} s"}
+    fir_rows, dft_rows = 8192, 768
+    st = synth.noise_stream(1, C, T, fir_rows, seed, fast=True)
+    x = oracle._as_c128(st.x)
+    h = st.h.astype("float64")
+    g = synth.complex_gaussian((1, fir_rows, C), seed + 1)
+    spec = g[:, :dft_rows]
+    oracle.fir(x[:, :T + 1], h)  # load the library, warm the threads
+
+    def parts():
+        out = {}
+        t0 = time.perf_counter()
+        oracle.fir(x, h)
+        out["fir"] = (time.perf_counter() - t0) / fir_rows
+        t0 = time.perf_counter()
+        oracle.dft(spec, -1)
+        out["dft"] = (time.perf_counter() - t0) / dft_rows
+        t0 = time.perf_counter()
+        oracle.dft(spec, +1)
+        out["inverse_dft"] = (time.perf_counter() - t0) / dft_rows
+        t0 = time.perf_counter()
+        oracle.fir_adjoint_x(g, h)
+        oracle.fir_adjoint_h(g, x, T)
+        out["fir_adjoints"] = (time.perf_counter() - t0) / fir_rows
+        return out
+
+    def report(per_row):
+        step = sum(per_row.values()) * B * S
+        res = {"value": round(B * S * C / step / 1e6, 4), "step_s": round(step, 2),
+               "fir_msamples_s": round(C / per_row["fir"] / 1e6, 2),
+               "fir_gflops": round(2 * C * (2 * T - 1) / per_row["fir"] / 1e9, 2),
+               "dft_msamples_s": round(C / per_row["dft"] / 1e6, 3),
+               "dft_gflops": round(8.0 * C * C / per_row["dft"] / 1e9, 2)}
+        return res
+
+    nthreads = oracle.num_threads()
+    all_cores = report(parts())
+    oracle.set_num_threads(1)
+    try:
+        one_core = report(parts())
+    finally:
+        oracle.set_num_threads(nthreads)
+    return {"value": all_cores["value"], "unit": "Msamples/s", "cores": nthreads, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": f"FP64 oracle parts timed separately on samples of the {B}x{S}-spectrum, C={C}, "
+                      f"T={T} step: FIR and both FIR adjoints on {fir_rows} spectra, DFT and inverse DFT "
+                      f"(direct O(C^2)) on {dft_rows} spectra, each scaled linearly to {B * S} spectra "
+                      f"(DFT parts extrapolated)",
+            "all_cores": all_cores, "one_core": one_core}
 
 
 def extras_sweep(dev, stream, C, S):
@@ -126,23 +179,48 @@ def extras_sweep(dev, stream, C, S):
     return out
 
 
+def precision_errors(dev, C, T, S):
+    """Error of each input type against FP64 on one seeded stream of S
+    spectra (C channels, T taps): `binding` is the GPU spectra against the
+    oracle on the same quantised input (the parity bar); `vs_unquantised` is
+    the GPU spectra against the oracle on the Gaussian before quantisation
+    (informational: it includes the quantisation noise itself)."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_1511_03599_amd import pfb, synth
+    out = {}
+    h = synth.windowed_sinc_taps(C, T)
+    hd = torch.from_numpy(h).to(dev)
+    for dt, sigma in (("ci8", 16.0), ("ci16", 2000.0), ("cf16", 1.0), ("c64", 1.0)):
+        xc = synth.complex_gaussian((1, S + T - 1, C), synth.seed_for(3, 50), sigma=sigma * np.sqrt(2.0)
+                                    if dt in ("ci8", "ci16") else 1.0)
+        xq = synth.quantise(xc, dt)
+        xd = torch.from_numpy(np.ascontiguousarray(xq)).to(dev)
+        if dt == "c64":
+            xd = torch.view_as_complex(xd).contiguous()
+        Y = pfb.Plan(C, T, S, 1, dt).execute(xd, hd).cpu().numpy().astype(np.complex128)
+        Yq = oracle.pfb_forward(xq, h)
+        Yc = oracle.pfb_forward(xc, h)
+        n = np.linalg.norm
+        out[dt] = {"binding_rel_l2": float(f"{n(Y - Yq) / n(Yq):.3e}"),
+                   "vs_unquantised_rel_l2": float(f"{n(Y - Yc) / n(Yc):.3e}")}
+    return out
+
+
 def extras_precision(dev, stream):
     """C=4096, T=16, 32768 spectra in each input type: FIR alone and the
-    whole filter bank; bytes use each type's sample size."""
-    import numpy as np
+    whole filter bank (device-generated inputs of each type's distribution);
+    bytes use each type's sample size. Errors per type on a 64-spectrum
+    sample."""
     import torch
     from paper_1511_03599_amd import metrics, pfb, synth
     C, T, S = 4096, 16, 32768
     out = {}
     Y = torch.empty((1, S, C), dtype=torch.complex64, device=dev)
+    h = torch.from_numpy(synth.windowed_sinc_taps(C, T)).to(dev)
     for dt in ("ci8", "ci16", "cf16", "c64"):
-        if dt == "c64":
-            st = synth.noise_stream(1, C, T, S, synth.seed_for(3, 3), fast=True)
-            x = torch.view_as_complex(torch.from_numpy(st.x)).to(dev).contiguous()
-        else:
-            st = synth.noise_stream(1, C, T, S, synth.seed_for(3, {"ci8": 0, "ci16": 1, "cf16": 2}[dt]), dtype=dt)
-            x = torch.from_numpy(np.ascontiguousarray(st.x)).to(dev)
-        h = torch.from_numpy(st.h).to(dev)
+        x = synth.device_quantised_noise((1, S + T - 1, C), dt, synth.seed_for(3, 10), dev)
         p = pfb.Plan(C, T, S, 1, dt)
         pf = pfb.Plan(C, T, S, 1, dt, pfb.FIR_ONLY)
         for _ in range(3):
@@ -153,8 +231,11 @@ def extras_precision(dev, stream):
         out[dt] = {"pfb_ms": round(tp, 4), "pfb_msamples_s": round(S * C / tp / 1e3, 1),
                    "pfb_gbs": round(metrics.pfb_fused_bytes(1, S, C, T, dt) / tp / 1e6, 1),
                    "fir_ms": round(tf, 4), "fir_gbs": round(metrics.fir_bytes(1, S, C, T, dt) / tf / 1e6, 1),
-                   "conversions_per_s": round(2 * (S + T - 1) * C / tf / 1e6, 1), "path": p.info()["path"]}
+                   "path": p.info()["path"]}
         del x, p, pf
+    err = precision_errors(dev, C, T, 64)
+    for dt in err:
+        out[dt].update(err[dt])
     return out
 
 
@@ -271,23 +352,24 @@ def extras_subbands(dev, stream):
     return out
 
 
-def extras_differentiable(dev, stream):
-    """32 streams x 8192 spectra, C=1024, T=16: forward, adjoint, and both."""
+def extras_single_stream(dev, stream):
+    """One stream of 65536 spectra, C=1024, T=16 (the tap-sweep workload at
+    16 taps): forward, adjoint and the fwd+bwd step, complex64 noise."""
     import torch
     from paper_1511_03599_amd import metrics, pfb, synth
-    B, S, C, T = 32, 8192, 1024, 16
-    x = synth.device_noise((B, S + T - 1, C), synth.seed_for(5, 1), dev)
+    B, S, C, T = 1, 65536, 1024, 16
+    x = synth.device_noise((B, S + T - 1, C), synth.seed_for(2, T), dev)
     h = torch.from_numpy(synth.windowed_sinc_taps(C, T)).to(dev)
-    gY = synth.device_noise((B, S, C), synth.seed_for(5, 2), dev)
+    gY = synth.device_noise((B, S, C), synth.seed_for(2, 100 + T), dev)
     Y = torch.empty((B, S, C), dtype=torch.complex64, device=dev)
     gx = torch.empty_like(x)
     gh = torch.empty((T, C), dtype=torch.float32, device=dev)
     p = pfb.Plan(C, T, S, B, "c64")
-    for _ in range(2):
+    for _ in range(3):
         p.execute(x, h, Y=Y)
         p.backward(x, h, gY, gx=gx, gh=gh)
-    tf = time_calls(lambda: p.execute(x, h, Y=Y), 10, stream)
-    tb = time_calls(lambda: p.backward(x, h, gY, gx=gx, gh=gh), 10, stream)
+    tf = time_calls(lambda: p.execute(x, h, Y=Y), 20, stream)
+    tb = time_calls(lambda: p.backward(x, h, gY, gx=gx, gh=gh), 20, stream)
     fb, bb = metrics.pfb_fused_bytes(B, S, C, T), metrics.backward_fused_bytes(B, S, C, T)
     return {"fwd_ms": round(tf, 4), "bwd_ms": round(tb, 4), "fwd_gbs": round(fb / tf / 1e6, 1),
             "bwd_gbs": round(bb / tb / 1e6, 1), "fwd_bwd_msamples_s": round(B * S * C / (tf + tb) / 1e3, 1)}
@@ -296,13 +378,9 @@ def extras_differentiable(dev, stream):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--taps", type=int, default=16)
-    ap.add_argument("--channels", type=int, default=1024)
-    ap.add_argument("--spectra", type=int, default=65536)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=49152)
     ap.add_argument("--quick", action="store_true", help="only the headline step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with three plain 512 MiB device copies (counter calibration for profiles)")
@@ -318,13 +396,12 @@ def main():
 
     from paper_1511_03599_amd import metrics, pfb, synth
 
-    C, T, S, B = args.channels, args.taps, args.spectra, 1
+    B, S, C, T = 32, 8192, 1024, 16
     dev = torch.device("cuda:0")
-    log(f"bench: C={C} T={T} S={S} B={B}: generating input")
-    st = synth.noise_stream(B, C, T, S, synth.seed_for(2, T), fast=True)
-    x = torch.view_as_complex(torch.from_numpy(st.x)).to(dev).contiguous()
-    h = torch.from_numpy(st.h).to(dev)
-    gY = synth.device_noise((B, S, C), synth.seed_for(2, 100 + T), dev)
+    log(f"bench: B={B} S={S} C={C} T={T}: generating input")
+    x = synth.device_tone_streams(B, C, T, S, synth.seed_for(5), dev)
+    h = torch.from_numpy(synth.windowed_sinc_taps(C, T)).to(dev)
+    gY = synth.device_noise((B, S, C), synth.seed_for(5, 2), dev)
     Y = torch.empty((B, S, C), dtype=torch.complex64, device=dev)
     gx = torch.empty((B, S + T - 1, C), dtype=torch.complex64, device=dev)
     gh = torch.empty((T, C), dtype=torch.float32, device=dev)
@@ -349,10 +426,10 @@ def main():
     # per-call times of the two halves (same stream, HIP events)
     t_fwd = time_calls(lambda: plan.execute(x, h, Y=Y), args.steps, stream)
     t_bwd = time_calls(lambda: plan.backward(x, h, gY, gx=gx, gh=gh), args.steps, stream)
-    for _ in range(args.warmup):
+    for _ in range(2):
         step(plain)
-    t_plain = time_calls(lambda: step(plain), args.steps, stream)
-    t_plain_fwd = time_calls(lambda: plain.execute(x, h, Y=Y), args.steps, stream)
+    t_plain = time_calls(lambda: step(plain), max(3, args.steps // 4), stream)
+    t_plain_fwd = time_calls(lambda: plain.execute(x, h, Y=Y), max(3, args.steps // 4), stream)
     torch.cuda.synchronize()
     log(f"bench: fwd {t_fwd:.4f} ms, bwd {t_bwd:.4f} ms, plain step {t_plain:.4f} ms")
 
@@ -367,10 +444,10 @@ def main():
     if t_bwd >= t_fwd:
         name = {"fused": "fused_bwd_kernel+gh_reduce_kernel", "fused_ws": "fused_bwd_ws_kernel+gh_reduce_kernel",
                 "split": "split_adjoint"}[info["backward_kind"]]
-        t_dom, b_dom, tkey = t_bwd, bwd_bytes, f"pfb_backward_c{C}_t{T}_s{S}"
+        t_dom, b_dom, tkey = t_bwd, bwd_bytes, f"pfb_backward_b{B}_s{S}_c{C}_t{T}"
     else:
         name = "fused_fwd_kernel" if info["path"] == "fused" else "split_forward"
-        t_dom, b_dom, tkey = t_fwd, fwd_bytes, f"pfb_execute_c{C}_t{T}_s{S}"
+        t_dom, b_dom, tkey = t_fwd, fwd_bytes, f"pfb_execute_b{B}_s{S}_c{C}_t{T}"
     achieved = b_dom / (t_dom * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK, 4), "traffic": read_traffic(tkey), "kernel": name,
@@ -381,12 +458,16 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t_step, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"pfb fwd+bwd, {B} stream x {S} spectra, C={C}, T={T}, complex64 noise",
+        "config": {"workload": f"differentiable pfb fwd+bwd, {B} streams x {S} spectra, C={C}, T={T}, "
+                               f"complex64 off-centre tones, seeded gradient",
                    "channels": C, "taps": T, "spectra": S, "streams": B, "path": info["path"],
-                   "backward_fused": info["backward_fused"], "backward_kind": info["backward_kind"]},
+                   "backward_kind": info["backward_kind"], "fused_rows": info["fir_rows"],
+                   "backward_rows": info["backward_rows"]},
         "hbm_gbs": round(step_gbs, 1), "hbm_frac": round(step_gbs / HBM_PEAK, 4),
         "fwd_ms": round(t_fwd, 5), "bwd_ms": round(t_bwd, 5),
         "fwd_gbs": round(fwd_bytes / t_fwd / 1e6, 1), "bwd_gbs": round(bwd_bytes / t_bwd / 1e6, 1),
+        "fwd_frac": round(fwd_bytes / t_fwd / 1e6 / HBM_PEAK, 4),
+        "bwd_frac": round(bwd_bytes / t_bwd / 1e6 / HBM_PEAK, 4),
         "plain": {"ms_per_step": round(t_plain, 5), "value": round(samples / (t_plain * 1e-3) / 1e6, 1),
                   "fwd_ms": round(t_plain_fwd, 5), "speedup": round(t_plain / t_step, 3)},
         "roofline": roof,
@@ -394,9 +475,12 @@ def main():
     del plain
 
     if not args.quick:
-        log("bench: tap sweep")
-        extras = {"tap_sweep_c1024_s65536": extras_sweep(dev, stream, C, S)}
         del x, gx, gY, Y
+        torch.cuda.empty_cache()
+        log("bench: tap sweep")
+        extras = {"tap_sweep_c1024_s65536": extras_sweep(dev, stream, 1024, 65536)}
+        log("bench: single stream fwd+bwd")
+        extras["single_stream_b1_s65536_c1024_t16"] = extras_single_stream(dev, stream)
         torch.cuda.empty_cache()
         log("bench: low-precision inputs")
         extras["precision_c4096_t16_s32768"] = extras_precision(dev, stream)
@@ -404,8 +488,6 @@ def main():
         log("bench: batched beams")
         extras["batched_64_beams"] = extras_batched(dev, stream)
         torch.cuda.empty_cache()
-        log("bench: differentiable workload")
-        extras["differentiable_b32_s8192_c1024_t16"] = extras_differentiable(dev, stream)
         log("bench: mixed-radix channel counts")
         extras["mixed_radix_t16"] = extras_mixed_radix(dev, stream)
         torch.cuda.empty_cache()
@@ -425,7 +507,7 @@ def main():
 
     if not args.no_cpu:
         log("bench: timing the oracle on the host")
-        out["cpu_baseline"] = cpu_baseline(C, T, args.cpu_rows, synth.seed_for(2, 7))
+        out["cpu_baseline"] = cpu_baseline(B, S, C, T, synth.seed_for(5, 7))
     print(json.dumps(out), flush=True)
 
 

@@ -27,7 +27,9 @@ DTYPE_CODES = {"c64": 0, "ci16": 1, "ci8": 2, "cf16": 3}
 # flags
 FIR_ONLY, NO_FUSE, PLAIN, STREAMING = 1, 4, 8, 16
 PATH_NAMES = {0: "fused", 1: "split", 2: "fir_only"}
-MAX_TAPS = 64
+MAX_TAPS = 1024          # PFB_MAX_TAPS: forward and FIR-only plans
+MAX_TAPS_WINDOW = 64     # PFB_MAX_TAPS_WINDOW: backward and batched plans
+STORAGE_DTYPES = {"ci16": torch.int16, "ci8": torch.int8, "cf16": torch.float16}
 
 
 class PFBError(RuntimeError):
@@ -45,7 +47,7 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("fir_rows", ctypes.c_int32), ("fir_cpt", ctypes.c_int32),
                 ("padded_taps", ctypes.c_int32), ("workspace_bytes", ctypes.c_int64),
                 ("chunk_rows", ctypes.c_int64), ("backward_fused", ctypes.c_int32),
-                ("fused_ws", ctypes.c_int32)]
+                ("fused_ws", ctypes.c_int32), ("backward_rows", ctypes.c_int32)]
 
 
 EXPORTED = ("pfb_plan_create", "pfb_execute", "pfb_execute_stream", "pfb_stream_reset", "pfb_backward",
@@ -119,6 +121,49 @@ def dtype_of(x: torch.Tensor) -> str:
     return {torch.int16: "ci16", torch.int8: "ci8", torch.float16: "cf16"}[x.dtype]
 
 
+def _plain_tensor(t, name: str, cuda: bool):
+    """Common checks of a tensor handed to the library as a raw pointer."""
+    if not isinstance(t, torch.Tensor):
+        raise PFBError(PFB_E_INVALID, f"{name} must be a torch.Tensor")
+    if cuda and not t.is_cuda:
+        raise PFBError(PFB_E_INVALID, f"{name} must be a CUDA (HIP) tensor")
+    if t.is_conj() or t.is_neg():
+        # data_ptr() ignores the lazy conjugate / negative bits, so the
+        # kernels would read or fill the unconjugated values
+        raise PFBError(PFB_E_INVALID, f"{name} has its conjugate or negative bit set; "
+                                      "call resolve_conj() / resolve_neg() first")
+    if not t.is_contiguous():
+        raise PFBError(PFB_E_INVALID, f"{name} must be contiguous")
+
+
+def check_samples(x, B: int, rows: int, C: int, dtype: str, name: str = "x", cuda: bool = True,
+                  lead: tuple | None = None):
+    """A sample array of the plan's element type: complex64 [*lead] (or
+    float32 [*lead, 2]) for c64, [*lead, 2] of int16 / int8 / float16
+    otherwise; lead defaults to (B, rows, C). Raises PFBError otherwise."""
+    _plain_tensor(x, name, cuda)
+    lead = (B, rows, C) if lead is None else tuple(lead)
+    if dtype == "c64":
+        ok = (x.dtype == torch.complex64 and tuple(x.shape) == lead) or \
+             (x.dtype == torch.float32 and tuple(x.shape) == lead + (2,))
+        want = f"complex64 {list(lead)}"
+    else:
+        ok = x.dtype == STORAGE_DTYPES[dtype] and tuple(x.shape) == lead + (2,)
+        want = f"{STORAGE_DTYPES[dtype]} {list(lead + (2,))}"
+    if not ok:
+        raise PFBError(PFB_E_INVALID, f"{name} must be {want} for a {dtype} plan, "
+                                      f"got {x.dtype} {list(x.shape)}")
+
+
+def check_array(t, name: str, shape: tuple, dtype, cuda: bool = True, device=None):
+    """A dense array of exactly `shape` and `dtype` (on `device` if given)."""
+    _plain_tensor(t, name, cuda)
+    if t.dtype != dtype or tuple(t.shape) != tuple(shape):
+        raise PFBError(PFB_E_INVALID, f"{name} must be {dtype} {list(shape)}, got {t.dtype} {list(t.shape)}")
+    if device is not None and t.device != device:
+        raise PFBError(PFB_E_INVALID, f"{name} is on {t.device}, the other arguments on {device}")
+
+
 class Plan:
     """One filter-bank problem: B streams of S filtered spectra, C channels,
     T taps, input element type `dtype`."""
@@ -142,26 +187,24 @@ class Plan:
                 "padded_taps": i.padded_taps, "workspace_bytes": i.workspace_bytes,
                 "chunk_rows": i.chunk_rows, "backward_fused": bool(i.backward_fused),
                 "backward_kind": ("split", "fused", "fused_ws")[i.backward_fused],
-                "fused_ws": bool(i.fused_ws)}
+                "fused_ws": bool(i.fused_ws), "backward_rows": i.backward_rows}
 
     def _check_x(self, x):
-        want = (self.B, self.rows, self.C)
-        shp = tuple(x.shape[:3]) if x.dim() >= 3 else None
-        if not x.is_cuda or shp != want or not x.is_contiguous():
-            raise PFBError(PFB_E_INVALID, f"x must be a contiguous CUDA tensor of shape {want}(+2)")
-        if dtype_of(x) != self.dtype:
-            raise PFBError(PFB_E_INVALID, f"x dtype {x.dtype} does not match plan dtype {self.dtype}")
+        check_samples(x, self.B, self.rows, self.C, self.dtype)
 
-    def _check_h(self, h):
-        if not h.is_cuda or h.dtype != torch.float32 or tuple(h.shape) != (self.T, self.C) \
-                or not h.is_contiguous():
-            raise PFBError(PFB_E_INVALID, f"taps must be contiguous float32 CUDA [{self.T}, {self.C}]")
+    def _check_h(self, h, device=None):
+        check_array(h, "taps", (self.T, self.C), torch.float32, device=device)
+
+    def _check_out(self, t, name, device):
+        check_array(t, name, (self.B, self.S, self.C), torch.complex64, device=device)
 
     def execute(self, x, h, Y=None, y=None, stream=None):
         """Forward pass. Returns Y (or y for a FIR-only plan)."""
         self._check_x(x)
-        self._check_h(h)
+        self._check_h(h, x.device)
         out_shape = (self.B, self.S, self.C)
+        if y is not None:
+            self._check_out(y, "y", x.device)
         if self.flags & FIR_ONLY:
             if y is None:
                 y = torch.empty(out_shape, dtype=torch.complex64, device=x.device)
@@ -169,6 +212,8 @@ class Plan:
             return y
         if Y is None:
             Y = torch.empty(out_shape, dtype=torch.complex64, device=x.device)
+        else:
+            self._check_out(Y, "Y", x.device)
         check(lib().pfb_execute(self._h, _ptr(x), _ptr(h), _ptr(y), _ptr(Y), _stream(stream)))
         return Y
 
@@ -188,8 +233,10 @@ class Plan:
         if not self.flags & STREAMING:
             raise PFBError(PFB_E_STATE, "execute_stream needs a plan created with STREAMING")
         self._check_x(xbuf)
-        self._check_h(h)
+        self._check_h(h, xbuf.device)
         out_shape = (self.B, self.S, self.C)
+        if y is not None:
+            self._check_out(y, "y", xbuf.device)
         if self.flags & FIR_ONLY:
             if y is None:
                 y = torch.empty(out_shape, dtype=torch.complex64, device=xbuf.device)
@@ -197,6 +244,8 @@ class Plan:
             return y
         if Y is None:
             Y = torch.empty(out_shape, dtype=torch.complex64, device=xbuf.device)
+        else:
+            self._check_out(Y, "Y", xbuf.device)
         check(lib().pfb_execute_stream(self._h, _ptr(xbuf), _ptr(h), _ptr(y), _ptr(Y), _stream(stream)))
         return Y
 
@@ -207,16 +256,25 @@ class Plan:
     def backward(self, x, h, gY, gx=None, gh=None, want_gx=True, want_gh=True, stream=None):
         """Adjoint pass for a real loss with frequency-spectra gradient gY.
         Returns (gx, gh); either is None when not requested."""
-        self._check_h(h)
+        if self.dtype != "c64":
+            raise PFBError(PFB_E_UNSUPPORTED, "backward needs a complex64 plan")
+        check_array(gY, "gY", (self.B, self.S, self.C), torch.complex64)
+        dev = gY.device
+        self._check_h(h, dev)
         if want_gh or x is not None:
             self._check_x(x)
-        if gY.dtype != torch.complex64 or tuple(gY.shape) != (self.B, self.S, self.C) \
-                or not gY.is_contiguous():
-            raise PFBError(PFB_E_INVALID, "gY must be contiguous complex64 [B, S, C]")
-        if want_gx and gx is None:
-            gx = torch.empty((self.B, self.rows, self.C), dtype=torch.complex64, device=gY.device)
-        if want_gh and gh is None:
-            gh = torch.empty((self.T, self.C), dtype=torch.float32, device=gY.device)
+            if x.device != dev:
+                raise PFBError(PFB_E_INVALID, f"x is on {x.device}, gY on {dev}")
+        if want_gx:
+            if gx is None:
+                gx = torch.empty((self.B, self.rows, self.C), dtype=torch.complex64, device=dev)
+            else:
+                check_array(gx, "gx", (self.B, self.rows, self.C), torch.complex64, device=dev)
+        if want_gh:
+            if gh is None:
+                gh = torch.empty((self.T, self.C), dtype=torch.float32, device=dev)
+            else:
+                check_array(gh, "gh", (self.T, self.C), torch.float32, device=dev)
         check(lib().pfb_backward(self._h, _ptr(x), _ptr(h), _ptr(gY), _ptr(gx if want_gx else None),
                                  _ptr(gh if want_gh else None), _stream(stream)))
         return (gx if want_gx else None), (gh if want_gh else None)
@@ -268,13 +326,19 @@ class BatchedPlan:
         if Ys is None:
             Ys = [torch.empty((S, C), dtype=torch.complex64, device=xs[0].device)
                   for (C, T, S) in self.beams]
-        for (C, T, S), x, h, Y in zip(self.beams, xs, hs, Ys):
-            if x.dtype != torch.complex64 or tuple(x.shape[-2:]) != (S + T - 1, C) or not x.is_contiguous():
-                raise PFBError(PFB_E_INVALID, f"beam x must be contiguous complex64 [{S + T - 1}, {C}]")
-            if h.dtype != torch.float32 or tuple(h.shape) != (T, C) or not h.is_contiguous():
-                raise PFBError(PFB_E_INVALID, f"beam taps must be contiguous float32 [{T}, {C}]")
-            if Y.dtype != torch.complex64 or Y.numel() != S * C or not Y.is_contiguous():
-                raise PFBError(PFB_E_INVALID, f"beam Y must be contiguous complex64 [{S}, {C}]")
+        if len(Ys) != n:
+            raise PFBError(PFB_E_INVALID, "one Y tensor per beam")
+        dev = xs[0].device
+        for i, ((C, T, S), x, h, Y) in enumerate(zip(self.beams, xs, hs, Ys)):
+            lead = (S + T - 1, C) if x.dim() == 2 else (1, S + T - 1, C)
+            check_samples(x, 1, S + T - 1, C, "c64", name=f"x[{i}]", lead=lead)
+            check_array(h, f"taps[{i}]", (T, C), torch.float32, device=dev)
+            if x.device != dev:
+                raise PFBError(PFB_E_INVALID, f"x[{i}] is on {x.device}, x[0] on {dev}")
+            if Y.dim() == 2:
+                check_array(Y, f"Y[{i}]", (S, C), torch.complex64, device=dev)
+            else:
+                check_array(Y, f"Y[{i}]", (1, S, C), torch.complex64, device=dev)
         P = ctypes.c_void_p * n
         xa = P(*[x.data_ptr() for x in xs])
         ha = P(*[h.data_ptr() for h in hs])
@@ -308,13 +372,13 @@ class VegasPlan:
         self._h = h
 
     def execute(self, x, h, Y=None, stream=None):
-        want = (self.S + self.T - 1, self.NS, self.C, 2)
-        if not x.is_cuda or tuple(x.shape[:4]) != want or not x.is_contiguous():
-            raise PFBError(PFB_E_INVALID, f"x must be a contiguous CUDA tensor of shape {want}(+2)")
-        if not h.is_cuda or h.dtype != torch.float32 or tuple(h.shape) != (self.T, self.C) or not h.is_contiguous():
-            raise PFBError(PFB_E_INVALID, f"taps must be contiguous float32 CUDA [{self.T}, {self.C}]")
+        lead = (self.S + self.T - 1, self.NS, self.C, 2)
+        check_samples(x, 1, 0, 0, self.dtype, lead=lead)
+        check_array(h, "taps", (self.T, self.C), torch.float32, device=x.device)
         if Y is None:
             Y = torch.empty((self.S, self.NS, self.C, 2), dtype=torch.complex64, device=x.device)
+        else:
+            check_array(Y, "Y", (self.S, self.NS, self.C, 2), torch.complex64, device=x.device)
         check(lib().pfb_execute_vegas(self._h, _ptr(x), _ptr(h), _ptr(Y), _stream(stream)))
         return Y
 
@@ -399,8 +463,8 @@ class PFBFunction(torch.autograd.Function):
         B, rows, C = x.shape
         T = h.shape[0]
         plan = cached_plan(C, T, rows - T + 1, B, "c64", 0)
-        x = x.contiguous()
-        h = h.contiguous()
+        x = x.resolve_conj().resolve_neg().contiguous()
+        h = h.resolve_neg().contiguous()
         Y = plan.execute(x, h)
         ctx.save_for_backward(x, h)
         ctx.plan = plan
@@ -410,7 +474,8 @@ class PFBFunction(torch.autograd.Function):
     def backward(ctx, gY):
         x, h = ctx.saved_tensors
         need_x, need_h = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
-        gx, gh = ctx.plan.backward(x, h, gY.contiguous(), want_gx=need_x, want_gh=need_h)
+        gY = gY.resolve_conj().resolve_neg().contiguous()
+        gx, gh = ctx.plan.backward(x, h, gY, want_gx=need_x, want_gh=need_h)
         return gx, gh
 
 

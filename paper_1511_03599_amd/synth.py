@@ -203,6 +203,41 @@ def device_noise(shape, seed: int, device):
     return torch.randn(tuple(shape), dtype=torch.complex64, device=device, generator=g)
 
 
+def device_quantised_noise(shape, dtype: str, seed: int, device):
+    """Noise of the given storage type generated on the device (timing runs):
+    the same distributions as noise_stream (sigma 16 for int8, 2000 for int16
+    per real component, round half to even, symmetric clip; unit variance for
+    float16 and complex64), as a tensor in the library's layout (complex64
+    [shape], else [shape + (2,)] of the storage type)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    pair = torch.randn(tuple(shape) + (2,), dtype=torch.float32, device=device, generator=g)
+    if dtype == "ci8":
+        return torch.clamp(torch.round(pair * 16.0), -127, 127).to(torch.int8)
+    if dtype == "ci16":
+        return torch.clamp(torch.round(pair * 2000.0), -32767, 32767).to(torch.int16)
+    pair *= 1.0 / math.sqrt(2.0)
+    if dtype == "cf16":
+        return pair.to(torch.float16)
+    return torch.view_as_complex(pair)
+
+
+def device_tone_streams(B, C, T, S, seed, device):
+    """The differentiable workload's tone-only streams (tone_params, the
+    offset_tone formula), evaluated on the device in float64 and rounded once
+    to complex64 [B, S+T-1, C] (timing runs)."""
+    import torch
+    rows = S + T - 1
+    k, d, ph = tone_params(B, C, seed)
+    n = torch.arange(rows * C, dtype=torch.float64, device=device)
+    out = torch.empty((B, rows, C), dtype=torch.complex64, device=device)
+    for b in range(B):
+        ang = 2.0 * math.pi * float((k[b] + d[b]) / C) * n + float(ph[b])
+        out[b] = torch.polar(torch.ones_like(ang), ang).to(torch.complex64).reshape(rows, C)
+    return out
+
+
 def tone_params(B: int, C: int, seed: int):
     """Per-stream off-centre tones: bin k_b uniform in [0, C), offset delta_b
     uniform in +-[0.1, 0.4] bins, phase uniform in [0, 2 pi)."""

@@ -111,58 +111,6 @@ def test_autograd_function_leakage_loss(dev):
     assert rel_l2(c128(xr.grad), gx_r) <= GX_TOL
 
 
-def test_full_size_differentiable_sampled(dev):
-    """32 streams x 8192 spectra, C=1024, T=16 tones at full size: spectra and
-    the sample gradient on sampled rows against the oracle, and both
-    gradients against the adjoint identity over the whole problem."""
-    import torch
-    pfb = pfbmod()
-    st = synth.tone_streams()
-    B, S, C, T = st.B, st.S, st.C, st.T
-    say("full-size differentiable workload")
-    x = to_device(st.x, dev)
-    hd = taps_to_device(st.h, dev)
-    plan = pfb.Plan(C, T, S, B, "c64")
-    Y = plan.execute(x, hd)
-    mask = torch.ones((B, 1, C), device=dev)
-    for b, k in enumerate(st.tone_bins):
-        mask[b, 0, int(k)] = 0
-    gY = (2.0 * mask * Y).contiguous()
-    gx, gh = plan.backward(x, hd, gY)
-    torch.cuda.synchronize()
-    # forward spectra on sampled rows
-    g = synth.rng(5)
-    picks = [(0, 0), (B - 1, S - 1), (3, 255), (3, 256)] + [(int(g.integers(0, B)), int(g.integers(0, S)))
-                                                          for _ in range(6)]
-    for b, s in picks:
-        Yr = oracle.pfb_forward(st.x[b:b + 1, s:s + T], st.h)
-        assert rel_l2(c128(Y[b, s]), Yr[0, 0]) <= 1e-5
-    # sample gradient of row p needs gy rows p-T+1..p: use the GPU gY (its
-    # parity is the forward's) and the oracle adjoint over that window
-    gYh = c128(gY)
-    for b, p in [(0, 0), (1, 5), (B - 1, S + T - 2), (7, 4000)]:
-        s0, s1 = max(0, p - T + 1), min(S, p + 1)
-        gy_rows = oracle.dft(gYh[b, s0:s1], +1)
-        acc = np.zeros(C, dtype=np.complex128)
-        for s in range(s0, s1):
-            acc += st.h[p - s].astype(np.float64) * gy_rows[s - s0]
-        assert rel_l2(c128(gx[b, p]), acc) <= 1e-5, (b, p)
-    # the tap gradient at full size: the adjoint identity
-    # sum(gh * dh) = Re <gY, Y(x; dh)> for a random direction dh, with the
-    # forward's own parity established above (inner products in float64)
-    dh = taps_to_device(synth.random_taps(C, T, 741), dev)
-    Ydh = plan.execute(x, dh)
-    lhs = (gh.double() * dh.double()).sum().item()
-    rhs = (gY.real.double() * Ydh.real.double() + gY.imag.double() * Ydh.imag.double()).sum().item()
-    assert abs(lhs - rhs) <= 1e-4 * abs(rhs)
-    # and the sample gradient: sum Re(conj(gx) dx) = Re <gY, Y(dx; h)>
-    dx = torch.randn((B, S + T - 1, C), dtype=torch.complex64, device=dev)
-    Ydx = plan.execute(dx, hd)
-    lhs = (gx.real.double() * dx.real.double() + gx.imag.double() * dx.imag.double()).sum().item()
-    rhs = (gY.real.double() * Ydx.real.double() + gY.imag.double() * Ydx.imag.double()).sum().item()
-    assert abs(lhs - rhs) <= 1e-4 * abs(rhs)
-
-
 @pytest.mark.parametrize("C,T,S,B", [(1024, 16, 700, 2), (512, 8, 333, 1), (256, 4, 1000, 3), (1024, 5, 64, 1)])
 def test_wave_specialised_adjoint_equals_single_role(dev, C, T, S, B, tmp_path, monkeypatch):
     """Both fused adjoint kernels do the same operations in the same order:
