@@ -213,6 +213,31 @@ pfb_status pfb_execute_vegas(pfb_plan *plan, const void *x, const float *taps, v
 pfb_status pfb_backward(pfb_plan *plan, const void *x, const float *taps, const void *gY,
                         void *gx, float *gh, void *stream);
 
+/* Size of the device scratch of pfb_backward_noalloc (bytes, one per GPU). */
+#define PFB_NOALLOC_SCRATCH_BYTES (32u << 20)
+
+/*
+ * pfb_backward without a plan and without any allocation, for callers that
+ * cannot allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc. Same results as pfb_backward with a
+ * plan of the same descriptor (the same fused adjoint kernel and fixed-order
+ * tap-gradient reduction; its twiddle table is computed on the device by
+ * every call, in FP64 rounded once, like the plan's host-built table).
+ *   desc  C in {256, 512, 1024}, T <= 16, dtype PFB_C64, flags 0; other
+ *         descriptors return PFB_E_UNSUPPORTED (or PFB_E_INVALID).
+ *   x, taps, gY, gx, gh  as for pfb_backward (gx or gh may be NULL).
+ * The library keeps the twiddle table and the per-tile tap-gradient partials
+ * in a device array of PFB_NOALLOC_SCRATCH_BYTES per GPU, held until the
+ * process ends: batch * taps * channels * 4 bytes of partials must fit in it
+ * (at C=1024, T=16: up to 511 streams); larger problems return
+ * PFB_E_UNSUPPORTED before anything is enqueued. The call makes no hipMalloc,
+ * hipFree or other allocating call. All calls on one GPU share its array:
+ * calls that overlap on one GPU (different streams or threads) race; calls
+ * ordered on one stream are safe.
+ */
+pfb_status pfb_backward_noalloc(const pfb_desc *desc, const void *x, const float *taps, const void *gY,
+                                void *gx, float *gh, void *stream);
+
 /*
  * Many independent beams with their own C, T, S (one stream each, complex
  * float32, C a power of two in [32, 8192], T <= PFB_MAX_TAPS_WINDOW) in one

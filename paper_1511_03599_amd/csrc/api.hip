@@ -851,6 +851,12 @@ extern "C" const char *pfb_last_error(void) { return g_last_error.c_str(); }
 
 // Internal hooks for the batched and tuning modules.
 pfb_status pfb_internal_fail(pfb_status st, const char *msg) { return fail(st, msg); }
+// gx rows per fused adjoint tile, as a plan chooses it (no tuning cache)
+int pfb_internal_bwd_tile_rows(int64_t B, int64_t S, int T, int C, int cus)
+{
+    const int sb = balanced_tile_rows(B, S + T - 1, 16, 128, cus);
+    return std::min(sb, view_rows_cap((int64_t)C * 8, 16, 0));
+}
 pfb_status pfb_internal_validate(const pfb_desc *d, bool batched_beam) { return validate_desc(d, batched_beam); }
 pfb_plan *pfb_internal_new_plan() { return new (std::nothrow) pfb_plan(); }
 void pfb_internal_set_batched(pfb_plan *p, Batched *b) { p->kind = KIND_BATCHED; p->batched = b; }

@@ -46,6 +46,7 @@ struct Batched;
 void batched_free(Batched *b);
 
 pfb_status pfb_internal_fail(pfb_status st, const char *msg);
+int pfb_internal_bwd_tile_rows(int64_t B, int64_t S, int T, int C, int cus);
 pfb_status pfb_internal_validate(const pfb_desc *d, bool batched_beam);
 pfb_plan *pfb_internal_new_plan();
 void pfb_internal_set_batched(pfb_plan *p, Batched *b);

@@ -51,7 +51,7 @@ class PlanInfo(ctypes.Structure):
 
 
 EXPORTED = ("pfb_plan_create", "pfb_execute", "pfb_execute_stream", "pfb_stream_reset", "pfb_backward",
-            "pfb_plan_create_batched", "pfb_execute_batched", "pfb_plan_create_vegas", "pfb_execute_vegas",
+            "pfb_backward_noalloc", "pfb_plan_create_batched", "pfb_execute_batched", "pfb_plan_create_vegas", "pfb_execute_vegas",
             "pfb_tune", "pfb_tune_batched", "pfb_plan_get_info", "pfb_plan_destroy", "pfb_status_str",
             "pfb_last_error")
 
@@ -75,6 +75,7 @@ def lib():
     L.pfb_plan_create_vegas.argtypes = [i32, i32, i32, ctypes.c_int64, i32, ctypes.POINTER(vp)]
     L.pfb_execute_vegas.argtypes = [vp, vp, vp, vp, vp]
     L.pfb_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.pfb_backward_noalloc.argtypes = [ctypes.POINTER(Desc), vp, vp, vp, vp, vp, vp]
     L.pfb_plan_create_batched.argtypes = [i32, ctypes.POINTER(Desc), ctypes.POINTER(vp)]
     L.pfb_execute_batched.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
     L.pfb_tune.argtypes = [ctypes.POINTER(Desc), ctypes.c_char_p]
@@ -86,7 +87,7 @@ def lib():
     L.pfb_last_error.argtypes = []
     L.pfb_last_error.restype = ctypes.c_char_p
     for f in ("pfb_plan_create", "pfb_execute", "pfb_execute_stream", "pfb_stream_reset", "pfb_backward",
-              "pfb_plan_create_batched", "pfb_execute_batched", "pfb_plan_create_vegas", "pfb_execute_vegas",
+              "pfb_backward_noalloc", "pfb_plan_create_batched", "pfb_execute_batched", "pfb_plan_create_vegas", "pfb_execute_vegas",
               "pfb_tune", "pfb_tune_batched", "pfb_plan_get_info", "pfb_plan_destroy"):
         getattr(L, f).restype = st
     _lib = L
@@ -439,6 +440,39 @@ class StreamPipeline:
                 self.ev_out[k].record(self.s_out)
             self.used[k] = True
         self.s_out.synchronize()
+
+
+def backward_noalloc(x, h, gY, gx=None, gh=None, want_gx=True, want_gh=True, stream=None):
+    """pfb_backward_noalloc: the adjoint without a plan and without device
+    allocation inside the library (outputs are allocated here unless given).
+    x: complex64 [B, S+T-1, C]; h: float32 [T, C]; gY: complex64 [B, S, C].
+    Returns (gx, gh); either is None when not requested."""
+    check_array(gY, "gY", tuple(gY.shape), torch.complex64)
+    if gY.dim() != 3:
+        raise PFBError(PFB_E_INVALID, "gY must be complex64 [B, S, C]")
+    B, S, C = gY.shape
+    T = h.shape[0] if h.dim() == 2 else -1
+    dev = gY.device
+    check_array(h, "taps", (T, C), torch.float32, device=dev)
+    rows = S + T - 1
+    if want_gh or x is not None:
+        check_samples(x, B, rows, C, "c64")
+        if x.device != dev:
+            raise PFBError(PFB_E_INVALID, f"x is on {x.device}, gY on {dev}")
+    if want_gx:
+        if gx is None:
+            gx = torch.empty((B, rows, C), dtype=torch.complex64, device=dev)
+        else:
+            check_array(gx, "gx", (B, rows, C), torch.complex64, device=dev)
+    if want_gh:
+        if gh is None:
+            gh = torch.empty((T, C), dtype=torch.float32, device=dev)
+        else:
+            check_array(gh, "gh", (T, C), torch.float32, device=dev)
+    d = make_desc(C, T, S, B, "c64", 0)
+    check(lib().pfb_backward_noalloc(ctypes.byref(d), _ptr(x), _ptr(h), _ptr(gY), _ptr(gx if want_gx else None),
+                                     _ptr(gh if want_gh else None), _stream(stream)))
+    return (gx if want_gx else None), (gh if want_gh else None)
 
 
 _plan_cache: dict = {}
