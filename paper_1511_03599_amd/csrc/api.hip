@@ -294,15 +294,15 @@ static int view_rows_cap(int64_t row_bytes, int rb, int extra)
     return (int)(cap < rb ? rb : (cap > INT32_MAX ? INT32_MAX / rb * rb : cap));
 }
 
-// Rows per fused tile: short tiles (four chunks) so that many workgroups
-// run in launch order and the resident ones sweep a narrow band of rows; the
-// halo rows they share with the previous tile are then still cached.
-static int choose_fused_sb(const pfb_desc &d, int rb)
+// Rows per fused tile: whole rounds over the workgroups that fit at once
+// (`slots`), at least 256 rows so that the T-1 halo rows a tile re-reads stay
+// a small fraction of its input (measured: 64-row tiles fetched 1.24x the
+// input bytes; their halo rows are not served by the cache, because
+// neighbouring tiles run at the same time and the halo is the start of one
+// tile's walk but the end of the other's).
+static int choose_fused_sb(const pfb_desc &d, int rb, int slots)
 {
-    int64_t sb = 4 * (int64_t)rb;
-    if (sb > d.spectra)
-        sb = ceil_div(d.spectra, rb) * rb;
-    return (int)sb;
+    return balanced_tile_rows(d.batch, d.spectra, rb, 256, slots);
 }
 
 static pfb_status plan_single(const pfb_desc *d, pfb_plan *p)
@@ -351,8 +351,11 @@ static pfb_status plan_single(const pfb_desc *d, pfb_plan *p)
             p->fused_ws = te.fused_ws != 0;
         // the wave-specialised kernel pays a pipeline fill per tile: longer
         // tiles, balanced over the CUs
+        // workgroups per CU at once: LDS-bound (two chunk buffers of C
+        // padded complex rows and the twiddles)
+        const int slots = p->num_cus * (p->log2c >= 10 ? 1 : 2);
         p->fused_sb = p->fused_ws ? balanced_tile_rows(d->batch, d->spectra, rb, 128, p->num_cus)
-                                  : choose_fused_sb(*d, rb);
+                                  : choose_fused_sb(*d, rb, slots);
         if (tuned && te.fused_sb >= rb && te.fused_sb % rb == 0)
             p->fused_sb = te.fused_sb;
     } else {

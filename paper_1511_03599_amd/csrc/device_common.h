@@ -136,6 +136,36 @@ __device__ __forceinline__ void load_packed(const void *base, int64_t i, Packed<
     }
 }
 
+// Load a packed fragment of V samples at byte offset `off` (32-bit, the
+// lane's own) from a wave-uniform base: the address is a scalar base plus a
+// zero-extended vector offset, which the memory instruction takes as is (no
+// per-lane 64-bit address arithmetic).
+template <int DT, int V>
+__device__ __forceinline__ void load_packed_off(const char *ubase, uint32_t off, Packed<DT, V> &p)
+{
+    constexpr int B = V * SampleBytes<DT>::value; // bytes
+    const char *a = ubase + off;
+    if constexpr (B == 2) {
+        p.w[0] = *reinterpret_cast<const uint16_t *>(a);
+    } else if constexpr (B == 4) {
+        p.w[0] = *reinterpret_cast<const uint32_t *>(a);
+    } else if constexpr (B == 8) {
+        const uint2 q = *reinterpret_cast<const uint2 *>(a);
+        p.w[0] = q.x;
+        p.w[1] = q.y;
+    } else {
+        static_assert(B % 16 == 0, "fragment size");
+#pragma unroll
+        for (int k = 0; k < B / 16; ++k) {
+            const uint4 q = reinterpret_cast<const uint4 *>(a)[k];
+            p.w[4 * k] = q.x;
+            p.w[4 * k + 1] = q.y;
+            p.w[4 * k + 2] = q.z;
+            p.w[4 * k + 3] = q.w;
+        }
+    }
+}
+
 template <int DT, int V> __device__ __forceinline__ void zero_packed(Packed<DT, V> &p)
 {
 #pragma unroll

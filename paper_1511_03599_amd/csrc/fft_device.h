@@ -167,6 +167,159 @@ __device__ __forceinline__ void fft_gather_first(int lane, Src &&src, float2 (&v
     });
 }
 
+// The twiddle-table pointer a transform's passes read through (see
+// fft_passes): opaque, so that the compiler does not hoist the twiddle loads
+// of every pass out of a caller's loop over rows and hold them all in
+// registers at once. For an LDS table only an offset is opaque, so the pointer
+// keeps its LDS origin; a global one is rebuilt as a global pointer (the
+// opaque value has lost its address space, and flat loads would also count
+// against the LDS counter).
+template <bool TW_LDS> __device__ __forceinline__ const float2 *fft_twiddle_base(const float2 *tw)
+{
+    if constexpr (TW_LDS) {
+        int z = 0;
+        asm volatile("" : "+v"(z));
+        return tw + z;
+    } else {
+        const float2 *twp_opaque = tw;
+        asm volatile("" : "+v"(twp_opaque));
+        return as_global(twp_opaque);
+    }
+}
+
+// First-pass inputs of one transform read from this group's padded LDS row
+// (the same elements, in the same register order, as fft_gather_first with
+// src(idx) = row[pad(idx)]). Element j + i*C/R of butterfly j = lane + G*q
+// sits at pad(j) + i*(C/R + C/R/16) because C/R is a multiple of 16, so each
+// butterfly needs one address and constant offsets (no per-element index
+// arithmetic).
+template <int LOG2C, int G, bool INV>
+__device__ __forceinline__ void fft_gather_first_lds(int lane, const float2 *row, float2 (&v)[FftShape<LOG2C, G>::E])
+{
+    using S = FftShape<LOG2C, G>;
+    constexpr int R = S::radix(0);
+    constexpr int NB = S::E / R;
+    constexpr int CR = S::C / R;
+    static_assert(CR % 16 == 0 && G % 16 == 0, "constant padded offsets");
+    const int pl = S::pad(lane);
+    sfor<NB>([&](auto q) PFB_INLINE {
+        const int pj = pl + decltype(q)::value * (G + G / 16);
+        sfor<R>([&](auto i) PFB_INLINE {
+            float2 t = row[pj + decltype(i)::value * (CR + CR / 16)];
+            if constexpr (INV)
+                t = conj2(t);
+            v[decltype(q)::value * R + decltype(i)::value] = t;
+        });
+    });
+}
+
+// Pass P of one transform whose first-pass inputs are already in v (see
+// fft_gather_first), in two halves so that callers may run other work
+// between them and between the passes of a transform (fft_passes runs them
+// back to back):
+//   fft_pass_gather   for P > 0, load this pass's inputs from the group's LDS
+//                     row into v;
+//   fft_pass_compute  apply the twiddles and the radix-R butterflies in
+//                     registers, then scatter to the LDS row (and synchronise
+//                     the group) or, for the last pass, hand every output
+//                     element to `dst(idx, v)`.
+// `twp` comes from fft_twiddle_base. A group of more than one wave must
+// synchronise between the two halves (fft_pass does).
+template <int LOG2C, int G, int P>
+__device__ __forceinline__ void fft_pass_gather(int lane, const float2 *lds, float2 (&v)[FftShape<LOG2C, G>::E])
+{
+    using S = FftShape<LOG2C, G>;
+    constexpr int C = S::C;
+    constexpr int E = S::E;
+    constexpr int R = S::radix(P);
+    constexpr int NB = E / R;
+    constexpr int CR = C / R;
+    static_assert(P > 0, "the first pass's inputs come from fft_gather_first");
+    const int plane = S::pad(lane);
+    sfor<NB>([&](auto q) PFB_INLINE {
+        const int j = lane + G * decltype(q)::value;
+        const int pj = S::template pad_at<G>(lane, plane, decltype(q)::value);
+        sfor<R>([&](auto i) PFB_INLINE {
+            v[decltype(q)::value * R + decltype(i)::value] = lds[S::template pad_at<CR>(j, pj, decltype(i)::value)];
+        });
+    });
+}
+
+template <int LOG2C, int G, bool INV, bool TW_LDS, int P, class Dst>
+__device__ __forceinline__ void fft_pass_compute(int lane, float2 *lds, const float2 *twp,
+                                                 float2 (&v)[FftShape<LOG2C, G>::E], Dst &&dst)
+{
+    using S = FftShape<LOG2C, G>;
+    constexpr int C = S::C;
+    constexpr int E = S::E;
+    constexpr int R = S::radix(P);
+    constexpr int L = S::stride(P);
+    constexpr int NB = E / R;
+    constexpr int CR = C / R;
+
+    // twiddle and butterfly
+    sfor<NB>([&](auto q) PFB_INLINE {
+        constexpr int Q = decltype(q)::value;
+        const int j = lane + G * Q;
+        if constexpr (L > 1 && TW_LDS) {
+            const int k = j & (L - 1);
+            constexpr int PO = S::pass_offset(P);
+            sfor<R - 1>([&](auto ic) PFB_INLINE {
+                constexpr int i = decltype(ic)::value + 1;
+                v[Q * R + i] = cmul(v[Q * R + i], twp[PO + i * L + k]);
+            });
+        } else if constexpr (L > 1) {
+            const int k = j & (L - 1);
+            constexpr int PO = S::pass_offset(P);
+            const float4 *wp = reinterpret_cast<const float4 *>(twp + PO + k * R);
+            sfor<R / 2>([&](auto hh) PFB_INLINE {
+                constexpr int H = decltype(hh)::value;
+                const float4 w2 = wp[H];
+                if constexpr (H > 0)
+                    v[Q * R + 2 * H] = cmul(v[Q * R + 2 * H], make_float2(w2.x, w2.y));
+                v[Q * R + 2 * H + 1] = cmul(v[Q * R + 2 * H + 1], make_float2(w2.z, w2.w));
+            });
+        }
+        Dft<R>::run(&v[Q * R]);
+    });
+
+    // scatter
+    if constexpr (P == S::NPASS - 1) {
+        sfor<NB>([&](auto q) PFB_INLINE {
+            const int j = lane + G * decltype(q)::value;
+            sfor<R>([&](auto i) PFB_INLINE {
+                float2 t = v[decltype(q)::value * R + decltype(i)::value];
+                if constexpr (INV)
+                    t = conj2(t);
+                dst(j + decltype(i)::value * CR, t);
+            });
+        });
+    } else {
+        sfor<NB>([&](auto q) PFB_INLINE {
+            const int j = lane + G * decltype(q)::value;
+            const int k = j & (L - 1);
+            const int o = (j - k) * R + k;
+            const int po = S::pad(o);
+            sfor<R>([&](auto i) PFB_INLINE {
+                lds[S::template pad_at<L>(o, po, decltype(i)::value)] = v[decltype(q)::value * R + decltype(i)::value];
+            });
+        });
+        group_sync<G>();
+    }
+}
+
+template <int LOG2C, int G, bool INV, bool SRC_IN_LDS, bool TW_LDS, int P, class Dst>
+__device__ __forceinline__ void fft_pass(int lane, float2 *lds, const float2 *twp,
+                                         float2 (&v)[FftShape<LOG2C, G>::E], Dst &&dst)
+{
+    using S = FftShape<LOG2C, G>;
+    if constexpr (P > 0)
+        fft_pass_gather<LOG2C, G, P>(lane, lds, v);
+    if constexpr (G > 64 && P < S::NPASS - 1 && (P > 0 || SRC_IN_LDS))
+        group_sync<G>(); // every lane has read before any lane overwrites
+    fft_pass_compute<LOG2C, G, INV, TW_LDS, P>(lane, lds, twp, v, dst);
+}
+
 // The passes of one transform whose first-pass inputs are already in v (see
 // fft_gather_first); `dst(idx, v)` receives output element idx from the last
 // pass. When SRC_IN_LDS the inputs were read from this group's own LDS row,
@@ -182,96 +335,9 @@ __device__ __forceinline__ void fft_passes(int lane, float2 *lds, const float2 *
                                            float2 (&v)[FftShape<LOG2C, G>::E], Dst &&dst)
 {
     using S = FftShape<LOG2C, G>;
-    constexpr int C = S::C;
-    constexpr int E = S::E;
-    // Opaque twiddle address: keeps the compiler from hoisting the twiddle
-    // loads of every pass out of a caller's loop over rows, which would hold
-    // them all in registers at once. For an LDS table only an offset is
-    // opaque, so the pointer keeps its LDS origin; a global one is rebuilt as
-    // a global pointer (the opaque value has lost its address space, and
-    // flat loads would also count against the LDS counter).
-    const float2 *twp;
-    if constexpr (TW_LDS) {
-        int z = 0;
-        asm volatile("" : "+v"(z));
-        twp = tw + z;
-    } else {
-        const float2 *twp_opaque = tw;
-        asm volatile("" : "+v"(twp_opaque));
-        twp = as_global(twp_opaque);
-    }
-
+    const float2 *twp = fft_twiddle_base<TW_LDS>(tw);
     sfor<S::NPASS>([&](auto pp) PFB_INLINE {
-        constexpr int P = decltype(pp)::value;
-        constexpr int R = S::radix(P);
-        constexpr int L = S::stride(P);
-        constexpr int NB = E / R;
-        constexpr int CR = C / R;
-
-        // gather (the first pass's inputs are already in v)
-        if constexpr (P > 0) {
-            const int plane = S::pad(lane);
-            sfor<NB>([&](auto q) PFB_INLINE {
-                const int j = lane + G * decltype(q)::value;
-                const int pj = S::template pad_at<G>(lane, plane, decltype(q)::value);
-                sfor<R>([&](auto i) PFB_INLINE {
-                    v[decltype(q)::value * R + decltype(i)::value] =
-                        lds[S::template pad_at<CR>(j, pj, decltype(i)::value)];
-                });
-            });
-        }
-        if constexpr (G > 64 && P < S::NPASS - 1 && (P > 0 || SRC_IN_LDS))
-            group_sync<G>(); // every lane has read before any lane overwrites
-
-        // twiddle and butterfly
-        sfor<NB>([&](auto q) PFB_INLINE {
-            constexpr int Q = decltype(q)::value;
-            const int j = lane + G * Q;
-            if constexpr (L > 1 && TW_LDS) {
-                const int k = j & (L - 1);
-                constexpr int PO = S::pass_offset(P);
-                sfor<R - 1>([&](auto ic) PFB_INLINE {
-                    constexpr int i = decltype(ic)::value + 1;
-                    v[Q * R + i] = cmul(v[Q * R + i], twp[PO + i * L + k]);
-                });
-            } else if constexpr (L > 1) {
-                const int k = j & (L - 1);
-                constexpr int PO = S::pass_offset(P);
-                const float4 *wp = reinterpret_cast<const float4 *>(twp + PO + k * R);
-                sfor<R / 2>([&](auto hh) PFB_INLINE {
-                    constexpr int H = decltype(hh)::value;
-                    const float4 w2 = wp[H];
-                    if constexpr (H > 0)
-                        v[Q * R + 2 * H] = cmul(v[Q * R + 2 * H], make_float2(w2.x, w2.y));
-                    v[Q * R + 2 * H + 1] = cmul(v[Q * R + 2 * H + 1], make_float2(w2.z, w2.w));
-                });
-            }
-            Dft<R>::run(&v[Q * R]);
-        });
-
-        // scatter
-        if constexpr (P == S::NPASS - 1) {
-            sfor<NB>([&](auto q) PFB_INLINE {
-                const int j = lane + G * decltype(q)::value;
-                sfor<R>([&](auto i) PFB_INLINE {
-                    float2 t = v[decltype(q)::value * R + decltype(i)::value];
-                    if constexpr (INV)
-                        t = conj2(t);
-                    dst(j + decltype(i)::value * CR, t);
-                });
-            });
-        } else {
-            sfor<NB>([&](auto q) PFB_INLINE {
-                const int j = lane + G * decltype(q)::value;
-                const int k = j & (L - 1);
-                const int o = (j - k) * R + k;
-                const int po = S::pad(o);
-                sfor<R>([&](auto i) PFB_INLINE {
-                    lds[S::template pad_at<L>(o, po, decltype(i)::value)] = v[decltype(q)::value * R + decltype(i)::value];
-                });
-            });
-            group_sync<G>();
-        }
+        fft_pass<LOG2C, G, INV, SRC_IN_LDS, TW_LDS, decltype(pp)::value>(lane, lds, twp, v, dst);
     });
 }
 

@@ -15,8 +15,8 @@ bool fused_supported(int dtype, int tp, int log2c)
 
 int fused_rows_per_chunk(int tp, int log2c)
 {
-    (void)log2c;
-    return 16 > tp ? 16 : tp;
+    (void)tp;
+    return fused_pipe_rows(log2c);
 }
 
 hipError_t launch_fused(const FusedArgs &a, int dtype, int tp, int log2c, hipStream_t st)

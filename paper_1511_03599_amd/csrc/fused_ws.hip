@@ -1,6 +1,6 @@
 // Fused polyphase FIR + FFT with specialised waves.
 //
-// Same arithmetic as fused_fwd_kernel (fused.hip), in the same order, so the
+// Same arithmetic as fused_fwd_pipe_kernel (fused_launch.h), in the same order, so the
 // two kernels give identical bits: the FIR of Algorithm 1 followed by the
 // DFT of Sec. 2, Eq. (2), with the filtered spectra kept on chip.
 //
