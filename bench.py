@@ -209,10 +209,15 @@ def precision_errors(dev, C, T, S):
 
 
 def extras_precision(dev, stream):
-    """C=4096, T=16, 32768 spectra in each input type: FIR alone and the
-    whole filter bank (device-generated inputs of each type's distribution);
-    bytes use each type's sample size. Errors per type on a 64-spectrum
-    sample."""
+    """C=4096, T=16, 32768 spectra in each input type (device-generated
+    inputs of each type's distribution): the FIR alone and the whole filter
+    bank; the FIR alone again with four input buffers used in turn (about
+    1.1 GB of int8 input and more for the other types, beyond the 256 MB
+    last-level cache, so every call reads its input from HBM); and the
+    convert-per-use comparator (each stored sample converted at every tap,
+    2T conversions per output) beside this library's convert-at-load FIR (2
+    conversions per input sample). Bytes use each type's sample size.
+    Errors per type on a 64-spectrum sample."""
     import torch
     from paper_1511_03599_amd import metrics, pfb, synth
     C, T, S = 4096, 16, 32768
@@ -220,7 +225,8 @@ def extras_precision(dev, stream):
     Y = torch.empty((1, S, C), dtype=torch.complex64, device=dev)
     h = torch.from_numpy(synth.windowed_sinc_taps(C, T)).to(dev)
     for dt in ("ci8", "ci16", "cf16", "c64"):
-        x = synth.device_quantised_noise((1, S + T - 1, C), dt, synth.seed_for(3, 10), dev)
+        xs = [synth.device_quantised_noise((1, S + T - 1, C), dt, synth.seed_for(3, 10 + k), dev) for k in range(4)]
+        x = xs[0]
         p = pfb.Plan(C, T, S, 1, dt)
         pf = pfb.Plan(C, T, S, 1, dt, pfb.FIR_ONLY)
         for _ in range(3):
@@ -228,11 +234,34 @@ def extras_precision(dev, stream):
             pf.execute(x, h, y=Y)
         tp = time_calls(lambda: p.execute(x, h, Y=Y), 10, stream)
         tf = time_calls(lambda: pf.execute(x, h, y=Y), 10, stream)
-        out[dt] = {"pfb_ms": round(tp, 4), "pfb_msamples_s": round(S * C / tp / 1e3, 1),
-                   "pfb_gbs": round(metrics.pfb_fused_bytes(1, S, C, T, dt) / tp / 1e6, 1),
-                   "fir_ms": round(tf, 4), "fir_gbs": round(metrics.fir_bytes(1, S, C, T, dt) / tf / 1e6, 1),
-                   "path": p.info()["path"]}
-        del x, p, pf
+        k = [0]
+
+        def rotating():
+            pf.execute(xs[k[0] % 4], h, y=Y)
+            k[0] += 1
+        tr = time_calls(rotating, 12, stream)
+        fb = metrics.fir_bytes(1, S, C, T, dt)
+        r = {"pfb_ms": round(tp, 4), "pfb_msamples_s": round(S * C / tp / 1e3, 1),
+             "pfb_gbs": round(metrics.pfb_fused_bytes(1, S, C, T, dt) / tp / 1e6, 1),
+             "fir_ms": round(tf, 4), "fir_gbs": round(fb / tf / 1e6, 1),
+             "fir_rotating_inputs_ms": round(tr, 4), "fir_rotating_inputs_gbs": round(fb / tr / 1e6, 1),
+             "path": p.info()["path"]}
+        if dt != "c64":
+            pu = pfb.Plan(C, T, S, 1, dt, pfb.FIR_ONLY | pfb.CONVERT_PER_USE)
+            for _ in range(2):
+                pu.execute(x, h, y=Y)
+            tu = time_calls(lambda: pu.execute(x, h, y=Y), 10, stream)
+            at_load = 2 * (S + T - 1) * C
+            per_use = 2 * T * S * C
+            r.update({"fir_convert_per_use_ms": round(tu, 4), "fir_convert_per_use_gbs": round(fb / tu / 1e6, 1),
+                      "per_use_slowdown": round(tu / tf, 3),
+                      "conversions_at_load": at_load, "conversions_per_use": per_use,
+                      "gconversions_s_at_load": round(at_load / tf / 1e6, 1),
+                      "gconversions_s_per_use": round(per_use / tu / 1e6, 1)})
+            del pu
+        out[dt] = r
+        del x, xs, p, pf
+        torch.cuda.empty_cache()
     err = precision_errors(dev, C, T, 64)
     for dt in err:
         out[dt].update(err[dt])
@@ -382,6 +411,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="only the headline step")
+    ap.add_argument("--only", choices=["precision"], default=None,
+                    help="run only the named extra and print it as the JSON line (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with three plain 512 MiB device copies (counter calibration for profiles)")
     args = ap.parse_args()
@@ -395,6 +426,12 @@ def main():
     import torch
 
     from paper_1511_03599_amd import metrics, pfb, synth
+
+    if args.only == "precision":
+        dev = torch.device("cuda:0")
+        print(json.dumps({"precision_c4096_t16_s32768": extras_precision(dev, torch.cuda.current_stream())}),
+              flush=True)
+        return
 
     B, S, C, T = 32, 8192, 1024, 16
     dev = torch.device("cuda:0")

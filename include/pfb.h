@@ -80,9 +80,18 @@ enum {
     PFB_PLAIN = 8u,         /* the untuned single-stream comparator: one FIR
                                launch over the whole stream into a workspace,
                                then one FFT launch; no fusion, no chunking   */
-    PFB_STREAMING = 16u     /* the plan carries the last T-1 raw spectra of
+    PFB_STREAMING = 16u,    /* the plan carries the last T-1 raw spectra of
                                each stream from one pfb_execute_stream call
                                to the next (real-time use, Sec. 5)          */
+    PFB_CONVERT_PER_USE = 32u /* comparator for the conversion study of
+                               Sec. 4.2: the FIR converts each 8- or 16-bit
+                               sample at every tap that uses it (2T
+                               conversions per output, as a kernel that
+                               re-reads its window from a cache or shared
+                               memory does) instead of once when it is
+                               loaded. Same results. Needs an int16, int8 or
+                               float16 plan with T <= 16; forces the split
+                               path. PFB_E_UNSUPPORTED otherwise.          */
 };
 
 /* Limits. */

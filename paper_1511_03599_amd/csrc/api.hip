@@ -198,9 +198,11 @@ static pfb_status validate_desc(const pfb_desc *d, bool batched_beam)
         return fail(PFB_E_INVALID, "batch must be >= 1");
     if (bytes_per_sample(d->dtype) == 0)
         return fail(PFB_E_INVALID, "unknown dtype");
-    const uint32_t known = PFB_FIR_ONLY | PFB_NO_FUSE | PFB_PLAIN | PFB_STREAMING;
+    const uint32_t known = PFB_FIR_ONLY | PFB_NO_FUSE | PFB_PLAIN | PFB_STREAMING | PFB_CONVERT_PER_USE;
     if (!batched_beam && (d->flags & ~known))
         return fail(PFB_E_INVALID, "unknown flag bits");
+    if (!batched_beam && (d->flags & PFB_CONVERT_PER_USE) && (d->dtype == PFB_C64 || d->taps > 16))
+        return fail(PFB_E_UNSUPPORTED, "PFB_CONVERT_PER_USE needs int16, int8 or float16 input and T <= 16");
     const bool fir_only = !batched_beam && (d->flags & PFB_FIR_ONLY);
     if (!fir_only) {
         const int l2 = ilog2_exact(d->channels);
@@ -343,7 +345,8 @@ static pfb_status plan_single(const pfb_desc *d, pfb_plan *p)
 
     if (fir_only) {
         p->path = PATH_FIR_ONLY;
-    } else if (!(d->flags & (PFB_NO_FUSE | PFB_PLAIN)) && fused_supported(d->dtype, p->tp, p->log2c) &&
+    } else if (!(d->flags & (PFB_NO_FUSE | PFB_PLAIN | PFB_CONVERT_PER_USE)) &&
+               fused_supported(d->dtype, p->tp, p->log2c) &&
                !(tuned && te.path == PATH_SPLIT)) {
         p->path = PATH_FUSED;
         const int rb = fused_rows_per_chunk(p->tp, p->log2c);
@@ -511,7 +514,7 @@ static hipError_t run_fir(const pfb_plan *p, const void *x, const float *h, floa
         a.shift = 0;
         return launch_fir_long(a, d.dtype, st);
     }
-    return launch_fir(a, d.dtype, p->tp, p->fir_cpt, false, st);
+    return launch_fir(a, d.dtype, p->tp, p->fir_cpt, false, st, (d.flags & PFB_CONVERT_PER_USE) != 0);
 }
 
 static hipError_t run_fft(const pfb_plan *p, const float2 *in, float2 *out, int64_t nrows, int64_t rows_per_group,

@@ -208,6 +208,28 @@ __device__ __forceinline__ void unpack(const Packed<DT, V> &p, float2 (&o)[V])
     }
 }
 
+// Convert sample k of a packed fragment to float32, at every call: the
+// stored word passes through an opaque register copy first, so the compiler
+// cannot reuse an earlier conversion of the same word (used by the
+// convert-per-use comparator, which converts each sample at every tap).
+template <int DT, int V> __device__ __forceinline__ float2 unpack_one_fresh(const Packed<DT, V> &p, int k)
+{
+    if constexpr (DT == DT_C64) {
+        return make_float2(__uint_as_float(p.w[2 * k]), __uint_as_float(p.w[2 * k + 1]));
+    } else if constexpr (DT == DT_CI16 || DT == DT_CF16) {
+        uint32_t w = p.w[k];
+        asm volatile("" : "+v"(w));
+        if constexpr (DT == DT_CI16)
+            return make_float2(s16lo(w), s16hi(w));
+        else
+            return h2f(w);
+    } else {
+        uint32_t w = p.w[k / 2];
+        asm volatile("" : "+v"(w));
+        return make_float2(s8b(w, 2 * (k % 2)), s8b(w, 2 * (k % 2) + 1));
+    }
+}
+
 // Load V consecutive samples starting at sample index i and convert them.
 template <int DT, int V> struct Loader {
     static __device__ __forceinline__ void load(const void *base, int64_t i, float2 (&o)[V])

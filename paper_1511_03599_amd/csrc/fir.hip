@@ -119,19 +119,21 @@ __global__ __launch_bounds__(256) void gh_reduce_kernel(const float *__restrict_
 // Host launchers
 // ----------------------------------------------------------------------------
 
-hipError_t launch_fir(const FirArgs &a, int dtype, int tp, int cpt, bool rev, hipStream_t st)
+hipError_t launch_fir(const FirArgs &a, int dtype, int tp, int cpt, bool rev, hipStream_t st, bool per_use)
 {
     if (rev)
-        return dtype == DT_C64 ? launch_fir_adjoint(a, tp, cpt, st) : hipErrorInvalidValue;
+        return dtype == DT_C64 && !per_use ? launch_fir_adjoint(a, tp, cpt, st) : hipErrorInvalidValue;
+    if (per_use && (dtype == DT_C64 || tp > 16))
+        return hipErrorInvalidValue;
     switch (dtype) {
     case DT_C64:
         return launch_fir_dt<DT_C64, false>(a, tp, cpt, st);
     case DT_CI16:
-        return launch_fir_ci16(a, tp, cpt, st);
+        return launch_fir_ci16(a, tp, cpt, per_use, st);
     case DT_CI8:
-        return launch_fir_ci8(a, tp, cpt, st);
+        return launch_fir_ci8(a, tp, cpt, per_use, st);
     case DT_CF16:
-        return launch_fir_cf16(a, tp, cpt, st);
+        return launch_fir_cf16(a, tp, cpt, per_use, st);
     default:
         return hipErrorInvalidValue;
     }

@@ -1,11 +1,12 @@
-// Register-window FIR (fir_launch.h) for cf16 input.
+// Register-window FIR (fir_launch.h) for cf16 input, and its convert-per-use
+// comparator.
 #include "fir_launch.h"
 
 namespace pfb {
 
-hipError_t launch_fir_cf16(const FirArgs &a, int tp, int cpt, hipStream_t st)
+hipError_t launch_fir_cf16(const FirArgs &a, int tp, int cpt, bool per_use, hipStream_t st)
 {
-    return launch_fir_dt<DT_CF16, false>(a, tp, cpt, st);
+    return per_use ? launch_fir_per_use_dt<DT_CF16>(a, tp, cpt, st) : launch_fir_dt<DT_CF16, false>(a, tp, cpt, st);
 }
 
 } // namespace pfb

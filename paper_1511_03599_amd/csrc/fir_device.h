@@ -14,9 +14,16 @@ constexpr int fir_prefetch(int tp) { return tp <= 16 ? 16 : 8; }
 // One wave's task: wave task gw of a FIR launch (channel chunk fastest, then
 // tile, then stream). NT selects non-temporal stores (results that are not
 // read again soon) over plain ones (results read back by the same workgroup).
-template <int DT, int TP, int CPT, int D, bool REV, bool NT = true>
+// PER_USE selects the convert-per-use comparator (TP <= 16, low-precision
+// input): the window holds the samples as stored and each sample is
+// converted to float32 at every tap that uses it, 2T conversions per output,
+// as in a design that reads the window from a cache or shared memory at
+// every tap; otherwise each sample is converted once, when it enters the
+// window. Both give the same bits (the conversions are exact).
+template <int DT, int TP, int CPT, int D, bool REV, bool NT = true, bool PER_USE = false>
 __device__ __forceinline__ void fir_wave_task(const FirArgs &a, int64_t gw)
 {
+    static_assert(!PER_USE || (TP <= 16 && DT != DT_C64 && !REV), "convert-per-use comparator: TP <= 16");
     constexpr int U = TP > D ? TP : D; // outputs per unrolled step
     static_assert(U % TP == 0 && U % D == 0, "unroll");
     const int cch = (int)(gw % a.n_cchunks);
@@ -52,19 +59,40 @@ __device__ __forceinline__ void fir_wave_task(const FirArgs &a, int64_t gw)
         const int64_t rs = row < 0 ? 0 : (row < a.in_rows ? row : a.in_rows - 1);
         load_packed<DT, CPT>(xb, rs * a.C + cs, o);
     };
-    auto enter_masked = [&](const Packed<DT, CPT> &p, float2 (&wv)[CPT], int64_t row) {
-        unpack<DT, CPT>(p, wv);
-        const bool ok = active && row >= 0 && row < a.in_rows;
-        sfor<CPT>([&](auto k) PFB_INLINE { wv[k] = ok ? wv[k] : make_float2(0.0f, 0.0f); });
-    };
-
     float2 w[TP][CPT];
+    Packed<DT, CPT> wp[PER_USE ? TP : 1]; // the window as stored (PER_USE)
+    // a row entering the window: converted (or kept as stored, PER_USE),
+    // zeroed when outside the stream or the lane has no channel. The zeroing
+    // selects the stored words (all-zero words convert to +0.0 for every
+    // type) before the conversion, so the loaded words are always used and
+    // the compiler keeps every load unconditional (converting first and then
+    // selecting let it move each load and conversion under a branch, with a
+    // full wait after each load).
+    auto enter = [&](const Packed<DT, CPT> &p, auto slotc, int64_t row, bool test) PFB_INLINE {
+        constexpr int slot = decltype(slotc)::value;
+        const bool ok = !test || (active && row >= 0 && row < a.in_rows);
+        Packed<DT, CPT> m;
+        sfor<Packed<DT, CPT>::WORDS>([&](auto q) PFB_INLINE { m.w[q] = ok ? p.w[q] : 0u; });
+        if constexpr (PER_USE)
+            wp[slot] = m;
+        else
+            unpack<DT, CPT>(m, w[slot]);
+    };
+    // window sample of slot `slot`, channel k, for one tap
+    auto tap_in = [&](auto slotc, auto kc) PFB_INLINE -> float2 {
+        constexpr int slot = decltype(slotc)::value;
+        constexpr int k = decltype(kc)::value;
+        if constexpr (PER_USE)
+            return unpack_one_fresh<DT, CPT>(wp[slot], k);
+        else
+            return w[slot][k];
+    };
     Packed<DT, CPT> pf[D]; // prefetched rows, still packed
     sfor<TP - 1>([&](auto j) PFB_INLINE {
         Packed<DT, CPT> t;
         if constexpr (TP <= 16) {
             ldc(row0 + j, t);
-            enter_masked(t, w[j], row0 + j);
+            enter(t, j, row0 + j, true);
         } else {
             const int64_t r = row0 + j;
             if (active && r >= 0 && r < a.in_rows)
@@ -104,10 +132,10 @@ __device__ __forceinline__ void fir_wave_task(const FirArgs &a, int64_t gw)
             const int64_t row_in = row0 + o + TP - 1; // row entering the window
             if (KIND != TAIL || o < nout) {
                 if constexpr (KIND == TAIL) {
-                    enter_masked(pf[jj % D], w[(jj + TP - 1) % TP], row_in);
+                    enter(pf[jj % D], std::integral_constant<int, (jj + TP - 1) % TP>{}, row_in, true);
                     ldc(row_in + D, pf[jj % D]);
                 } else {
-                    unpack<DT, CPT>(pf[jj % D], w[(jj + TP - 1) % TP]);
+                    enter(pf[jj % D], std::integral_constant<int, (jj + TP - 1) % TP>{}, row_in, false);
                     if constexpr (KIND == FULL || jj < U - D)
                         load_packed<DT, CPT>(xb, (row_in + D) * a.C + c0, pf[jj % D]);
                 }
@@ -116,8 +144,9 @@ __device__ __forceinline__ void fir_wave_task(const FirArgs &a, int64_t gw)
                     float ar = 0.0f, ai = 0.0f;
                     sfor<TP>([&](auto jc) PFB_INLINE {
                         constexpr int j = decltype(jc)::value;
-                        ar = __builtin_fmaf(hp[k][j], w[(jj + j) % TP][k].x, ar);
-                        ai = __builtin_fmaf(hp[k][j], w[(jj + j) % TP][k].y, ai);
+                        const float2 xv = tap_in(std::integral_constant<int, (jj + j) % TP>{}, k);
+                        ar = __builtin_fmaf(hp[k][j], xv.x, ar);
+                        ai = __builtin_fmaf(hp[k][j], xv.y, ai);
                     });
                     acc[k] = make_float2(ar, ai);
                 });

@@ -9,7 +9,7 @@
 
 namespace pfb {
 
-template <int DT, int TP, int CPT, int D, bool REV>
+template <int DT, int TP, int CPT, int D, bool REV, bool PER_USE = false>
 __global__ __launch_bounds__(256, 2) void fir_kernel(FirArgs a)
 {
     // Consecutive waves take consecutive channel chunks, then consecutive
@@ -18,10 +18,10 @@ __global__ __launch_bounds__(256, 2) void fir_kernel(FirArgs a)
     const int64_t total = (int64_t)a.B * a.n_tiles * a.n_cchunks;
     if (gw >= total)
         return;
-    fir_wave_task<DT, TP, CPT, D, REV>(a, gw);
+    fir_wave_task<DT, TP, CPT, D, REV, true, PER_USE>(a, gw);
 }
 
-template <int DT, int TP, int CPT, bool REV>
+template <int DT, int TP, int CPT, bool REV, bool PER_USE = false>
 hipError_t launch_fir_t(const FirArgs &a, hipStream_t st)
 {
     constexpr int D = fir_prefetch(TP);
@@ -29,7 +29,7 @@ hipError_t launch_fir_t(const FirArgs &a, hipStream_t st)
     const int64_t blocks = (total + 3) / 4;
     if (blocks <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL((fir_kernel<DT, TP, CPT, D, REV>), dim3((unsigned)blocks), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((fir_kernel<DT, TP, CPT, D, REV, PER_USE>), dim3((unsigned)blocks), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
@@ -53,6 +53,23 @@ hipError_t launch_fir_dt(const FirArgs &a, int tp, int cpt, hipStream_t st)
         return hipErrorInvalidValue;
     }
 #undef PFB_FIR_CASE
+}
+
+// The convert-per-use comparator (fir_wave_task, PER_USE) for one
+// low-precision input type, padded taps <= 16.
+template <int DT> hipError_t launch_fir_per_use_dt(const FirArgs &a, int tp, int cpt, hipStream_t st)
+{
+#define PFB_FIR_PU_CASE(TPV)                                                                                 \
+    case TPV:                                                                                                \
+        return cpt == 2 ? launch_fir_t<DT, TPV, 2, false, true>(a, st) : launch_fir_t<DT, TPV, 1, false, true>(a, st);
+    switch (tp) {
+        PFB_FIR_PU_CASE(4)
+        PFB_FIR_PU_CASE(8)
+        PFB_FIR_PU_CASE(16)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef PFB_FIR_PU_CASE
 }
 
 } // namespace pfb

@@ -72,11 +72,12 @@ struct BwdArgs {
     int64_t S;
 };
 
-hipError_t launch_fir(const FirArgs &a, int dtype, int tp, int cpt, bool rev, hipStream_t st);
+// per_use: the convert-per-use comparator (low-precision input, tp <= 16)
+hipError_t launch_fir(const FirArgs &a, int dtype, int tp, int cpt, bool rev, hipStream_t st, bool per_use = false);
 // per input type (each in its own translation unit)
-hipError_t launch_fir_ci16(const FirArgs &a, int tp, int cpt, hipStream_t st);
-hipError_t launch_fir_ci8(const FirArgs &a, int tp, int cpt, hipStream_t st);
-hipError_t launch_fir_cf16(const FirArgs &a, int tp, int cpt, hipStream_t st);
+hipError_t launch_fir_ci16(const FirArgs &a, int tp, int cpt, bool per_use, hipStream_t st);
+hipError_t launch_fir_ci8(const FirArgs &a, int tp, int cpt, bool per_use, hipStream_t st);
+hipError_t launch_fir_cf16(const FirArgs &a, int tp, int cpt, bool per_use, hipStream_t st);
 hipError_t launch_fir_adjoint(const FirArgs &a, int tp, int cpt, hipStream_t st); // reversed taps, c64
 // FIR for T beyond the register window: tiles of 32 rows (SB = 32), one
 // channel per lane (64 per wave task), no tap padding (shift = 0).

@@ -25,7 +25,7 @@ PFB_OK, PFB_E_INVALID, PFB_E_UNSUPPORTED, PFB_E_NOMEM, PFB_E_HIP, PFB_E_STATE = 
 # pfb_dtype
 DTYPE_CODES = {"c64": 0, "ci16": 1, "ci8": 2, "cf16": 3}
 # flags
-FIR_ONLY, NO_FUSE, PLAIN, STREAMING = 1, 4, 8, 16
+FIR_ONLY, NO_FUSE, PLAIN, STREAMING, CONVERT_PER_USE = 1, 4, 8, 16, 32
 PATH_NAMES = {0: "fused", 1: "split", 2: "fir_only"}
 MAX_TAPS = 1024          # PFB_MAX_TAPS: forward and FIR-only plans
 MAX_TAPS_WINDOW = 64     # PFB_MAX_TAPS_WINDOW: backward and batched plans

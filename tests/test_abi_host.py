@@ -58,6 +58,7 @@ def _create(L, **kw):
     ({"taps": 1025}, 2), ({"channels": 44}, 2), ({"channels": 16}, 2), ({"channels": 16384}, 2),
     ({"channels": 8190}, 2), ({"channels": 13 * 64}, 2),
     ({"dtype": "c64", "flags": 1 << 10}, 1),
+    ({"dtype": "c64", "flags": 32}, 2), ({"dtype": "ci8", "taps": 17, "flags": 32}, 2),
     ({"channels": 1 << 30, "spectra": 1 << 40, "flags": 1}, 1),
 ])
 def test_invalid_descriptors_rejected_on_host(L, kw, code):

@@ -317,3 +317,26 @@ def test_long_taps_pfb_parity(dev, C, T, S, B):
     with pytest.raises(pfb.PFBError):
         plan.backward(to_device(x, dev), taps_to_device(h, dev),
                       to_device(synth.quantise(synth.complex_gaussian((B, S, C), 1601), "c64"), dev))
+
+
+@pytest.mark.parametrize("dtype", ["ci8", "ci16", "cf16"])
+@pytest.mark.parametrize("C,T,S", [(4096, 16, 300), (1000, 7, 90), (256, 4, 40)])
+def test_convert_per_use_comparator_same_bits(dev, dtype, C, T, S):
+    """The convert-per-use FIR (each stored sample converted at every tap)
+    gives the same bits as converting once at load (the conversions are
+    exact), for the FIR alone and for the filter bank, and matches the
+    oracle."""
+    import torch
+    pfb = pfbmod()
+    say(f"convert per use {dtype} C={C} T={T} S={S}")
+    x, h = make(C, T, S, 1, dtype, 900 + C + T, taps="sinc")
+    xd, hd = to_device(x, dev), taps_to_device(h, dev)
+    y0 = pfb.Plan(C, T, S, 1, dtype, pfb.FIR_ONLY).execute(xd, hd)
+    y1 = pfb.Plan(C, T, S, 1, dtype, pfb.FIR_ONLY | pfb.CONVERT_PER_USE).execute(xd, hd)
+    assert torch.equal(y0, y1)
+    assert rel_l2(c128(y1), oracle.fir(x, h)[0]) <= FIR_TOL
+    p = pfb.Plan(C, T, S, 1, dtype, pfb.CONVERT_PER_USE)
+    assert p.info()["path"] == "split"
+    Y1 = p.execute(xd, hd)
+    Y0 = pfb.Plan(C, T, S, 1, dtype, pfb.NO_FUSE).execute(xd, hd)
+    assert torch.equal(Y0, Y1)
