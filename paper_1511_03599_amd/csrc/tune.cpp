@@ -8,6 +8,7 @@
 // built-in defaults rather than to an error.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -50,6 +51,12 @@ static thread_local const TuneEntry *g_override = nullptr;
 
 void tune_set_override(const TuneEntry *e) { g_override = e; }
 
+// The entry for a descriptor: the last line with the same arch, dtype, C and
+// T and the same B and S; failing that, the line with the same arch, dtype,
+// C and T whose B*S is nearest in ratio (the last of equals), from which only
+// the shape-independent choices carry over (path, FIR channels per lane, the
+// wave-specialised forms); tile heights, chunk sizes and the adjoint tile then
+// keep the built-in defaults, which are sized for the actual shape.
 bool tune_lookup(const pfb_desc &d, TuneEntry *out)
 {
     if (g_override) {
@@ -63,9 +70,11 @@ bool tune_lookup(const pfb_desc &d, TuneEntry *out)
     if (!f)
         return false;
     const std::string arch = device_arch_name();
+    const double want = std::log((double)d.batch * (double)d.spectra);
     char line[512];
-    bool found = false;
-    TuneEntry best;
+    bool exact = false, near = false;
+    double near_dist = 0.0;
+    TuneEntry best_exact, best_near;
     while (std::fgets(line, sizeof line, f)) {
         char a[64];
         int dt, C, T, B;
@@ -73,7 +82,7 @@ bool tune_lookup(const pfb_desc &d, TuneEntry *out)
         int used = 0;
         if (std::sscanf(line, "%63s %d %d %d %d %lld%n", a, &dt, &C, &T, &B, &S, &used) != 6)
             continue;
-        if (arch != a || dt != d.dtype || C != d.channels || T != d.taps || B != d.batch || S != d.spectra)
+        if (arch != a || dt != d.dtype || C != d.channels || T != d.taps || B < 1 || S < 1)
             continue;
         TuneEntry e;
         char *rest = line + used;
@@ -87,13 +96,33 @@ bool tune_lookup(const pfb_desc &d, TuneEntry *out)
             parse_kv(tok, "bwd_sb", &e.bwd_sb);
             parse_kv(tok, "bwd_ws", &e.bwd_ws);
         }
-        best = e; // the last matching line wins
-        found = true;
+        if (B == d.batch && S == d.spectra) {
+            best_exact = e; // the last matching line wins
+            exact = true;
+            continue;
+        }
+        const double dist = std::fabs(std::log((double)B * (double)S) - want);
+        if (!near || dist <= near_dist) {
+            best_near = e;
+            near_dist = dist;
+            near = true;
+        }
     }
     std::fclose(f);
-    if (found)
-        *out = best;
-    return found;
+    if (exact) {
+        *out = best_exact;
+        return true;
+    }
+    if (near) {
+        TuneEntry e;
+        e.path = best_near.path;
+        e.fir_cpt = best_near.fir_cpt;
+        e.fused_ws = best_near.fused_ws;
+        e.bwd_ws = best_near.bwd_ws;
+        *out = e;
+        return true;
+    }
+    return false;
 }
 
 static thread_local int g_batched_override = 0;

@@ -56,3 +56,28 @@ def test_damaged_cache_falls_back_to_defaults(dev, tmp_path, monkeypatch):
     monkeypatch.delenv("PFB_TUNE_CACHE")
     c = pfb.Plan(1024, 16, 512, 1, "c64").info()
     assert a == b == c
+
+
+def test_cache_entry_carries_over_to_other_lengths(dev, tmp_path, monkeypatch):
+    """An entry for one (B, S) serves other batch sizes and lengths of the
+    same dtype, C and T with its shape-independent choices (here the split
+    path) and the built-in tile sizes; other C or T are untouched; an exact
+    entry wins over a nearer one."""
+    import torch
+    from paper_1511_03599_amd import pfb
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    cache = tmp_path / "tune.txt"
+    cache.write_text(f"{arch} 0 1024 16 1 1000 path=1 fir_cpt=1 fir_sb=64 bwd_sb=64\n"
+                     f"{arch} 0 1024 16 2 3000 path=0 fused_sb=32\n")
+    monkeypatch.setenv("PFB_TUNE_CACHE", str(cache))
+    near = pfb.Plan(1024, 16, 900, 1, "c64").info()     # nearest: the (1, 1000) line
+    assert near["path"] == "split" and near["fir_cpt"] == 1
+    assert near["fir_rows"] == 32                        # the built-in FIR tile height, not 64
+    assert pfb.Plan(1024, 16, 2900, 2, "c64").info()["path"] == "fused"   # nearest: (2, 3000)
+    assert pfb.Plan(1024, 16, 3000, 2, "c64").info()["fir_rows"] == 32     # exact entry
+    assert pfb.Plan(1024, 8, 900, 1, "c64").info()["path"] == "fused"     # other T: defaults
+    st = synth.noise_stream(1, 1024, 16, 900, 950)
+    out = pfb.Plan(1024, 16, 900, 1, "c64").execute(to_device(st.x, dev), taps_to_device(st.h, dev))
+    for s in (0, 450, 899):
+        Yr = oracle.pfb_forward(st.x[:, s:s + 16], st.h)
+        assert rel_l2(c128(out[0, s]), Yr[0, 0]) <= SPEC_TOL
