@@ -411,7 +411,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="only the headline step")
-    ap.add_argument("--only", choices=["precision"], default=None,
+    ap.add_argument("--only", choices=["precision", "sweep"], default=None,
                     help="run only the named extra and print it as the JSON line (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with three plain 512 MiB device copies (counter calibration for profiles)")
@@ -430,6 +430,11 @@ def main():
     if args.only == "precision":
         dev = torch.device("cuda:0")
         print(json.dumps({"precision_c4096_t16_s32768": extras_precision(dev, torch.cuda.current_stream())}),
+              flush=True)
+        return
+    if args.only == "sweep":
+        dev = torch.device("cuda:0")
+        print(json.dumps({"tap_sweep_c1024_s65536": extras_sweep(dev, torch.cuda.current_stream(), 1024, 65536)}),
               flush=True)
         return
 

@@ -88,17 +88,25 @@ __device__ __forceinline__ void fir_wave_task(const FirArgs &a, int64_t gw)
             return w[slot][k];
     };
     Packed<DT, CPT> pf[D]; // prefetched rows, still packed
+    // TP > 16: a whole tile of U rows, every row it reads inside the stream
+    // and every lane on a channel (wave-uniform)
+    const bool tp_clean = TP > 16 && (cch + 1) * 64 * CPT <= a.C && nout == U && row0 >= 0 &&
+                          row0 + nout + TP - 2 < a.in_rows;
     sfor<TP - 1>([&](auto j) PFB_INLINE {
         Packed<DT, CPT> t;
         if constexpr (TP <= 16) {
             ldc(row0 + j, t);
             enter(t, j, row0 + j, true);
         } else {
-            const int64_t r = row0 + j;
-            if (active && r >= 0 && r < a.in_rows)
-                load_packed<DT, CPT>(xb, r * a.C + c0, t);
-            else
-                zero_packed<DT, CPT>(t);
+            if (tp_clean) {
+                load_packed<DT, CPT>(xb, (row0 + j) * a.C + c0, t);
+            } else {
+                const int64_t r = row0 + j;
+                if (active && r >= 0 && r < a.in_rows)
+                    load_packed<DT, CPT>(xb, r * a.C + c0, t);
+                else
+                    zero_packed<DT, CPT>(t);
+            }
             unpack<DT, CPT>(t, w[j]);
         }
     });
@@ -107,7 +115,9 @@ __device__ __forceinline__ void fir_wave_task(const FirArgs &a, int64_t gw)
             ldc(row0 + TP - 1 + k, pf[k]); // masked when the row enters the window
         } else {
             const int64_t r = row0 + TP - 1 + k;
-            if (k < nout && active && r >= 0 && r < a.in_rows)
+            if (tp_clean)
+                load_packed<DT, CPT>(xb, r * a.C + c0, pf[k]);
+            else if (k < nout && active && r >= 0 && r < a.in_rows)
                 load_packed<DT, CPT>(xb, r * a.C + c0, pf[k]);
             else
                 zero_packed<DT, CPT>(pf[k]);
@@ -174,12 +184,37 @@ __device__ __forceinline__ void fir_wave_task(const FirArgs &a, int64_t gw)
         }
         for (; base < nout; base += U)
             block(base, std::integral_constant<int, TAIL>{});
+    } else if (tp_clean) {
+        // Windows of 32 taps and more, a whole tile of U rows inside the
+        // stream with every lane on a channel (the common case): one block
+        // with every load issued unconditionally, so the compiler waits only
+        // for the row that enters the window and D rows stay in flight.
+        sfor<U>([&](auto jjc) PFB_INLINE {
+            constexpr int jj = decltype(jjc)::value;
+            const int64_t row_in = row0 + jj + TP - 1;
+            unpack<DT, CPT>(pf[jj % D], w[(jj + TP - 1) % TP]);
+            if constexpr (jj + D < U)
+                load_packed<DT, CPT>(xb, (row_in + D) * a.C + c0, pf[jj % D]);
+            float2 acc[CPT];
+            sfor<CPT>([&](auto k) PFB_INLINE {
+                float ar = 0.0f, ai = 0.0f;
+                sfor<TP>([&](auto jc) PFB_INLINE {
+                    constexpr int j = decltype(jc)::value;
+                    ar = __builtin_fmaf(hp[k][j], w[(jj + j) % TP][k].x, ar);
+                    ai = __builtin_fmaf(hp[k][j], w[(jj + j) % TP][k].y, ai);
+                });
+                acc[k] = make_float2(ar, ai);
+            });
+            if constexpr (NT)
+                store_c64_nt<CPT>(yb + (int64_t)jj * a.C, acc);
+            else
+                store_c64<CPT>(yb + (int64_t)jj * a.C, acc);
+        });
     } else {
-        // Windows of 32 taps and more: each row's 2T FMA per output hides
-        // the wait for its load, and the block kinds above (32-64 unrolled
-        // rows each) would cost a wave per SIMD in registers. One compact
-        // loop: rows outside the stream are not loaded but zeroed, and the
-        // prefetch stays inside the tile.
+        // Windows of 32 taps and more, anything else (ragged tiles, stream
+        // edges, the last partial channel chunk): one compact loop; rows
+        // outside the stream are not loaded but zeroed, and the prefetch
+        // stays inside the tile.
         for (int base = 0; base < nout; base += U) {
             sfor<U>([&](auto jjc) PFB_INLINE {
                 constexpr int jj = decltype(jjc)::value;
