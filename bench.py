@@ -42,29 +42,38 @@ def log(*a):
 
 def source_digest() -> str:
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1511_03599_amd", "csrc", "*"))):
+    src = os.path.join(ROOT, "paper_1511_03599_amd", "csrc")
+    files = [f for ext in ("*.hip", "*.h", "*.cpp") for f in glob.glob(os.path.join(src, ext))]
+    for f in sorted(files):
         with open(f, "rb") as fh:
             h.update(os.path.basename(f).encode())
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def read_traffic(name: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary
-    profiles/traffic_<name>.txt, or None when there is none or the kernel
-    sources changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{name}.txt")
+def read_profile(fname: str):
+    """The `key: value` lines of a committed rocprofv3 summary under
+    profiles/, or None when there is none or the kernel sources changed
+    since its counters were taken."""
+    path = os.path.join(ROOT, "profiles", fname)
     if not os.path.exists(path):
         return None
     kv = {}
     for line in open(path):
-        if ":" in line:
+        if ":" in line and not line.startswith(("|", "#", " ")):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
     if kv.get("source_digest") != source_digest():
         return None
+    return kv
+
+
+def read_traffic(name: str):
+    """HBM bytes per launch from profiles/traffic_<name>.txt (FETCH_SIZE +
+    WRITE_SIZE, calibrated), or None."""
+    kv = read_profile(f"traffic_{name}.txt")
     try:
-        return float(kv["hbm_bytes_per_call"])
+        return float(kv["hbm_bytes_per_call"]) if kv else None
     except (KeyError, ValueError):
         return None
 
@@ -265,6 +274,21 @@ def extras_precision(dev, stream):
     err = precision_errors(dev, C, T, 64)
     for dt in err:
         out[dt].update(err[dt])
+    # conversion instructions counted by rocprofv3 (SQ_INSTS_VALU_CVT, per
+    # wave instruction, x64 lanes) in the committed summary of this workload
+    kv = read_profile("conversions_fir_c4096_t16_s32768.txt")
+    if kv:
+        for dt in ("ci8", "ci16", "cf16"):
+            try:
+                at = float(kv[f"{dt}.at_load.cvt_per_input_sample"])
+                pu = float(kv[f"{dt}.per_use.cvt_per_input_sample"])
+            except (KeyError, ValueError):
+                continue
+            n_in = (S + T - 1) * C
+            r = out[dt]
+            r["counted_cvt_per_input_sample"] = {"at_load": at, "per_use": pu}
+            r["counted_gconversions_s_at_load"] = round(at * n_in / r["fir_ms"] / 1e6, 1)
+            r["counted_gconversions_s_per_use"] = round(pu * n_in / r["fir_convert_per_use_ms"] / 1e6, 1)
     return out
 
 
@@ -404,6 +428,17 @@ def extras_single_stream(dev, stream):
             "bwd_gbs": round(bb / tb / 1e6, 1), "fwd_bwd_msamples_s": round(B * S * C / (tf + tb) / 1e3, 1)}
 
 
+def calibration_copies(dev):
+    """Three plain 512 MiB device-to-device copies: the known traffic that
+    scales the FETCH_SIZE and WRITE_SIZE counters in the profiles."""
+    import torch
+    a = torch.empty(1 << 26, dtype=torch.complex64, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -411,7 +446,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="only the headline step")
-    ap.add_argument("--only", choices=["precision", "sweep"], default=None,
+    ap.add_argument("--only", choices=["precision", "sweep", "batched"], default=None,
                     help="run only the named extra and print it as the JSON line (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with three plain 512 MiB device copies (counter calibration for profiles)")
@@ -427,15 +462,18 @@ def main():
 
     from paper_1511_03599_amd import metrics, pfb, synth
 
-    if args.only == "precision":
+    if args.only:
         dev = torch.device("cuda:0")
-        print(json.dumps({"precision_c4096_t16_s32768": extras_precision(dev, torch.cuda.current_stream())}),
-              flush=True)
-        return
-    if args.only == "sweep":
-        dev = torch.device("cuda:0")
-        print(json.dumps({"tap_sweep_c1024_s65536": extras_sweep(dev, torch.cuda.current_stream(), 1024, 65536)}),
-              flush=True)
+        stream = torch.cuda.current_stream()
+        if args.only == "precision":
+            res = {"precision_c4096_t16_s32768": extras_precision(dev, stream)}
+        elif args.only == "sweep":
+            res = {"tap_sweep_c1024_s65536": extras_sweep(dev, stream, 1024, 65536)}
+        else:
+            res = {"batched_64_beams": extras_batched(dev, stream)}
+        if args.copy_calibration:
+            calibration_copies(dev)
+        print(json.dumps(res), flush=True)
         return
 
     B, S, C, T = 32, 8192, 1024, 16
@@ -488,7 +526,8 @@ def main():
                 "split": "split_adjoint"}[info["backward_kind"]]
         t_dom, b_dom, tkey = t_bwd, bwd_bytes, f"pfb_backward_b{B}_s{S}_c{C}_t{T}"
     else:
-        name = "fused_fwd_kernel" if info["path"] == "fused" else "split_forward"
+        name = {"fused": "fused_fwd_ws_kernel" if info["fused_ws"] else "fused_fwd_pipe_kernel"}.get(
+            info["path"], "split_forward")
         t_dom, b_dom, tkey = t_fwd, fwd_bytes, f"pfb_execute_b{B}_s{S}_c{C}_t{T}"
     achieved = b_dom / (t_dom * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK, "unit": "GB/s",
@@ -541,11 +580,7 @@ def main():
         out["extras"] = extras
 
     if args.copy_calibration:
-        a = torch.empty(1 << 26, dtype=torch.complex64, device=dev)
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
+        calibration_copies(dev)
 
     if not args.no_cpu:
         log("bench: timing the oracle on the host")

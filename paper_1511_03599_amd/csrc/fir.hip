@@ -93,26 +93,37 @@ __global__ __launch_bounds__(256) void gh_partial_kernel(GhArgs a)
 
 // Tap gradient, second stage: gh[t][c] = sum over all tiles of the partials.
 // Tile p goes to running sum p mod 4 (each sum takes its tiles in ascending
-// order, the tail tiles beyond a multiple of four go to the first one), and
-// the four sums are combined as (s0 + s1) + (s2 + s3): a fixed order, so the
-// result is bit-reproducible.
+// order), and the four sums are combined as (s0 + s1) + (s2 + s3): a fixed
+// order, so the result is bit-reproducible. A block of four waves covers 64
+// consecutive elements; wave w keeps running sum w of each of them, so the
+// partials are read by four times as many waves as there are element groups.
 __global__ __launch_bounds__(256) void gh_reduce_kernel(const float *__restrict__ part, float *__restrict__ gh,
                                                         int64_t n_parts, int64_t tc)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= tc)
-        return;
-    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
-    int64_t p = 0;
-    for (; p + 4 <= n_parts; p += 4) {
-        s0 += part[(p + 0) * tc + i];
-        s1 += part[(p + 1) * tc + i];
-        s2 += part[(p + 2) * tc + i];
-        s3 += part[(p + 3) * tc + i];
+    __shared__ float sums[4][64];
+    const int w = wave_id(), l = lane_id();
+    const int64_t i = (int64_t)blockIdx.x * 64 + l;
+    float acc = 0.0f;
+    if (i < tc) {
+        // eight partials loaded ahead of their additions, which stay in
+        // ascending tile order
+        int64_t p = w;
+        for (; p + 28 < n_parts; p += 32) {
+            float v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                v[k] = part[(p + 4 * k) * tc + i];
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                acc += v[k];
+        }
+        for (; p < n_parts; p += 4)
+            acc += part[p * tc + i];
     }
-    for (; p < n_parts; ++p)
-        s0 += part[p * tc + i];
-    gh[i] = (s0 + s1) + (s2 + s3);
+    sums[w][l] = acc;
+    __syncthreads();
+    if (w == 0 && i < tc)
+        gh[i] = (sums[0][l] + sums[1][l]) + (sums[2][l] + sums[3][l]);
 }
 
 // ----------------------------------------------------------------------------
@@ -168,8 +179,7 @@ hipError_t launch_gh(const GhArgs &a, int tp, float *gh, hipStream_t st)
 
 hipError_t launch_gh_reduce(const float *part, float *gh, int64_t n_parts, int64_t tc, hipStream_t st)
 {
-    hipLaunchKernelGGL(gh_reduce_kernel, dim3((unsigned)((tc + 255) / 256)), dim3(256), 0, st, part, gh, n_parts,
-                       tc);
+    hipLaunchKernelGGL(gh_reduce_kernel, dim3((unsigned)((tc + 63) / 64)), dim3(256), 0, st, part, gh, n_parts, tc);
     return hipGetLastError();
 }
 
