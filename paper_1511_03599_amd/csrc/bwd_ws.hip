@@ -130,7 +130,7 @@ __global__ __launch_bounds__((WsShape<LOG2C, TP>::NT)) void fused_bwd_ws_kernel(
                 if (k + 1 < nchunks)
                     issue(k + 1);
                 float2 *row = gy_buf + (buf * RB + r) * PADDED;
-                fft_passes<LOG2C, G, true, false>(lane, row, a.tw, v,
+                fft_passes<LOG2C, G, true, false, false, false>(lane, row, a.tw, v,
                                                   [&](int idx, float2 t) { row[S::pad(idx)] = t; });
             };
             issue(0);
@@ -162,7 +162,7 @@ __global__ __launch_bounds__((WsShape<LOG2C, TP>::NT)) void fused_bwd_ws_kernel(
                     });
                 }
                 float2 *row = gy_buf + (buf * RB + r) * PADDED;
-                fft_passes<LOG2C, G, true, false>(lane, row, a.tw, v,
+                fft_passes<LOG2C, G, true, false, false, false>(lane, row, a.tw, v,
                                                   [&](int idx, float2 t) { row[S::pad(idx)] = t; });
                 if (want_gh) {
                     sfor<W::XQ - XH>([&](auto ec) PFB_INLINE {

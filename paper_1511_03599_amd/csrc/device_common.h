@@ -366,5 +366,9 @@ template <int V> __device__ __forceinline__ void buf_store_c64_nt(const BufView 
 // Lane and wave indices for 1-D blocks.
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
 __device__ __forceinline__ int wave_id() { return (int)(threadIdx.x >> 6); }
+// The same index as a wave-uniform (scalar) value: the compiler cannot see
+// that threadIdx.x >> 6 is uniform, and otherwise keeps everything derived
+// from it (tile, row and address bases) in vector registers.
+__device__ __forceinline__ int wave_id_uniform() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
 
 } // namespace pfb

@@ -245,9 +245,36 @@ __device__ __forceinline__ void fft_pass_gather(int lane, const float2 *lds, flo
     });
 }
 
-template <int LOG2C, int G, bool INV, bool TW_LDS, int P, class Dst>
+// The twiddles of pass P > 0 from the global table for this lane's
+// butterflies: R/2 aligned 16-byte vectors per butterfly, E/2 in all for
+// every pass (E/R butterflies of R entries). Issued one pass ahead by
+// fft_passes, so that their latency hides behind the previous pass instead
+// of following a barrier.
+template <int LOG2C, int G, int P>
+__device__ __forceinline__ void fft_load_twiddles(int lane, const float2 *twp,
+                                                  float4 (&w)[FftShape<LOG2C, G>::E / 2])
+{
+    using S = FftShape<LOG2C, G>;
+    constexpr int R = S::radix(P);
+    constexpr int L = S::stride(P);
+    constexpr int NB = S::E / R;
+    constexpr int PO = S::pass_offset(P);
+    static_assert(P > 0 && L > 1, "the first pass has no twiddles");
+    sfor<NB>([&](auto q) PFB_INLINE {
+        constexpr int Q = decltype(q)::value;
+        const int k = (lane + G * Q) & (L - 1);
+        const float4 *wp = reinterpret_cast<const float4 *>(twp + PO + k * R);
+        sfor<R / 2>([&](auto hh) PFB_INLINE { w[Q * (R / 2) + decltype(hh)::value] = wp[decltype(hh)::value]; });
+    });
+}
+
+// TWR: the pass's twiddles are already in `wpre` (fft_load_twiddles);
+// otherwise they are read here, from the LDS copy (TW_LDS) or the global
+// table.
+template <int LOG2C, int G, bool INV, bool TW_LDS, int P, class Dst, bool TWR = false>
 __device__ __forceinline__ void fft_pass_compute(int lane, float2 *lds, const float2 *twp,
-                                                 float2 (&v)[FftShape<LOG2C, G>::E], Dst &&dst)
+                                                 float2 (&v)[FftShape<LOG2C, G>::E], Dst &&dst,
+                                                 const float4 *wpre = nullptr)
 {
     using S = FftShape<LOG2C, G>;
     constexpr int C = S::C;
@@ -261,7 +288,15 @@ __device__ __forceinline__ void fft_pass_compute(int lane, float2 *lds, const fl
     sfor<NB>([&](auto q) PFB_INLINE {
         constexpr int Q = decltype(q)::value;
         const int j = lane + G * Q;
-        if constexpr (L > 1 && TW_LDS) {
+        if constexpr (L > 1 && TWR) {
+            sfor<R / 2>([&](auto hh) PFB_INLINE {
+                constexpr int H = decltype(hh)::value;
+                const float4 w2 = wpre[Q * (R / 2) + H];
+                if constexpr (H > 0)
+                    v[Q * R + 2 * H] = cmul(v[Q * R + 2 * H], make_float2(w2.x, w2.y));
+                v[Q * R + 2 * H + 1] = cmul(v[Q * R + 2 * H + 1], make_float2(w2.z, w2.w));
+            });
+        } else if constexpr (L > 1 && TW_LDS) {
             const int k = j & (L - 1);
             constexpr int PO = S::pass_offset(P);
             sfor<R - 1>([&](auto ic) PFB_INLINE {
@@ -330,15 +365,39 @@ __device__ __forceinline__ void fft_pass(int lane, float2 *lds, const float2 *tw
 // consecutive entries; LDS reads are counted apart from the caller's global
 // loads and stores, whereas a wait for a global twiddle load also waits for
 // every load and store issued before it.
-template <int LOG2C, int G, bool INV, bool SRC_IN_LDS, bool TW_LDS = false, class Dst>
+// TW_AHEAD (global table, transforms over several waves): request each
+// pass's twiddles one pass early (2E more registers live), so that their
+// latency is not exposed after every workgroup barrier; a caller short of
+// registers turns it off. A one-wave transform has no barrier to expose it
+// and keeps its registers.
+template <int LOG2C, int G, bool INV, bool SRC_IN_LDS, bool TW_LDS = false, bool TW_AHEAD = true, class Dst>
 __device__ __forceinline__ void fft_passes(int lane, float2 *lds, const float2 *__restrict__ tw,
                                            float2 (&v)[FftShape<LOG2C, G>::E], Dst &&dst)
 {
     using S = FftShape<LOG2C, G>;
     const float2 *twp = fft_twiddle_base<TW_LDS>(tw);
-    sfor<S::NPASS>([&](auto pp) PFB_INLINE {
-        fft_pass<LOG2C, G, INV, SRC_IN_LDS, TW_LDS, decltype(pp)::value>(lane, lds, twp, v, dst);
-    });
+    if constexpr (TW_LDS || !TW_AHEAD || G <= 64 || S::NPASS < 2) {
+        sfor<S::NPASS>([&](auto pp) PFB_INLINE {
+            fft_pass<LOG2C, G, INV, SRC_IN_LDS, TW_LDS, decltype(pp)::value>(lane, lds, twp, v, dst);
+        });
+    } else {
+        // Global table: the twiddles of pass P+1 are requested as pass P
+        // starts (those of pass 1 before the first pass), in two register
+        // sets used alternately.
+        float4 tw_odd[S::E / 2], tw_even[S::E / 2];
+        fft_load_twiddles<LOG2C, G, 1>(lane, twp, tw_odd);
+        sfor<S::NPASS>([&](auto pp) PFB_INLINE {
+            constexpr int P = decltype(pp)::value;
+            if constexpr (P > 0)
+                fft_pass_gather<LOG2C, G, P>(lane, lds, v);
+            if constexpr (P > 0 && P + 1 < S::NPASS)
+                fft_load_twiddles<LOG2C, G, P + 1>(lane, twp, (P + 1) % 2 ? tw_odd : tw_even);
+            if constexpr (G > 64 && P < S::NPASS - 1 && (P > 0 || SRC_IN_LDS))
+                group_sync<G>(); // every lane has read before any lane overwrites
+            fft_pass_compute<LOG2C, G, INV, false, P, Dst &, true>(lane, lds, twp, v, dst,
+                                                                   P % 2 ? tw_odd : tw_even);
+        });
+    }
 }
 
 // Run one transform. `src(idx)` returns input element idx (first pass);

@@ -14,7 +14,10 @@ __global__ __launch_bounds__(256, 2) void fir_kernel(FirArgs a)
 {
     // Consecutive waves take consecutive channel chunks, then consecutive
     // tiles, so the waves resident at any time sweep one narrow band of rows.
-    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave_id();
+    // Up to 16 taps the task index is made scalar, so that row and address
+    // bases stay in scalar registers (above that the longer windows
+    // allocate better from the vector form).
+    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (TP <= 16 ? wave_id_uniform() : wave_id());
     const int64_t total = (int64_t)a.B * a.n_tiles * a.n_cchunks;
     if (gw >= total)
         return;
