@@ -294,7 +294,7 @@ def extras_precision(dev, stream):
 
 def extras_batched(dev, stream):
     """64 beams of uneven C, T, S: one persistent launch vs 64 separate plain
-    launches on one stream."""
+    launches, and vs 64 launches of the default plans, on one stream."""
     import torch
     from paper_1511_03599_amd import metrics, pfb, synth
     beams = synth.beam_table()
@@ -314,12 +314,24 @@ def extras_batched(dev, stream):
             p.execute(x[None], h, Y=Y[None])
     run_plain()
     tpl = time_calls(run_plain, 3, stream)
+    del plains
+    # the same beams as 64 launches of this library's default plans (fused
+    # where the beam allows, else the split path with its default tiles)
+    defaults = [pfb.Plan(C, T, S, 1, "c64") for (C, T, S) in desc]
+
+    def run_default():
+        for p, x, h, Y in zip(defaults, xs, hs, Ys):
+            p.execute(x[None], h, Y=Y[None])
+    run_default()
+    tdf = time_calls(run_default, 3, stream)
+    del defaults
     samples = sum(S * C for (C, T, S) in desc)
     fused_bytes = sum(metrics.pfb_fused_bytes(1, S, C, T) for (C, T, S) in desc)
     return {"beams": len(desc), "msamples": round(samples / 1e6, 1), "ms": round(tb, 3),
             "msamples_s": round(samples / tb / 1e3, 1), "gbs": round(fused_bytes / tb / 1e6, 1),
             "frac_hbm": round(fused_bytes / tb / 1e6 / HBM_PEAK, 4),
-            "plain_64_launches_ms": round(tpl, 3), "speedup_vs_plain": round(tpl / tb, 3)}
+            "plain_64_launches_ms": round(tpl, 3), "speedup_vs_plain": round(tpl / tb, 3),
+            "default_64_launches_ms": round(tdf, 3)}
 
 
 def extras_streaming(dev, stream):
