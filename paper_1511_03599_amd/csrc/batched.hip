@@ -41,7 +41,7 @@ namespace pfb {
 constexpr int BT_THREADS = 512;          // threads per persistent workgroup
 constexpr int BT_WAVES = BT_THREADS / 64;
 constexpr int BT_TASK_ROWS = 32;         // filtered spectra per FIR wave task
-constexpr int BT_LDS = 8704;             // float2: the largest transform round
+constexpr int BT_LDS = 17408;            // float2: the largest transform round
 constexpr int BT_MAX_TAPS = PFB_MAX_TAPS_WINDOW;
 
 struct BeamInfo {

@@ -10,7 +10,7 @@ namespace pfb {
 template <int LOG2C> struct FftKernelShape {
     using FL = FftLanes<LOG2C>;
     static constexpr int G = FL::G;
-    static constexpr int NT = G > 256 ? G : 256; // threads per block
+    static constexpr int NT = G > 64 ? G : 256; // threads per block (one row when G > 64)
     static constexpr int F = NT / G;             // rows per block
     // waves per SIMD the register allocation must allow (launch-bounds
     // minimum): 4 lets two 512-thread blocks (C = 8192) share a CU, which

@@ -1,5 +1,5 @@
 // Stockham autosort FFT for one C-point transform held by a group of G lanes
-// (C a power of two, E = C/G elements per lane, E in {4, 8, 16}).
+// (C a power of two, E = C/G elements per lane, E in {8, 16, 32}).
 //
 // The transform is the DFT of Sec. 2, Eq. (2): unnormalised, bins in natural
 // order, exp(-2 pi i n m / C). The inverse (exp(+...), unnormalised) is the
@@ -27,31 +27,35 @@
 
 namespace pfb {
 
-// cos(2 pi e / 16) and sin(2 pi e / 16).
-constexpr float cos16(int e)
+// cos(2 pi e / 32) and sin(2 pi e / 32).
+constexpr float cos32(int e)
 {
-    constexpr float c[16] = {1.0f, 0.92387953251128674f, 0.70710678118654757f, 0.38268343236508978f,
-                             0.0f, -0.38268343236508978f, -0.70710678118654757f, -0.92387953251128674f,
-                             -1.0f, -0.92387953251128674f, -0.70710678118654757f, -0.38268343236508978f,
-                             0.0f, 0.38268343236508978f, 0.70710678118654757f, 0.92387953251128674f};
-    return c[e & 15];
+    constexpr float c[32] = {1.0f, 0.98078528040323045f, 0.92387953251128674f, 0.83146961230254524f,
+                             0.70710678118654757f, 0.55557023301960222f, 0.38268343236508978f, 0.19509032201612827f,
+                             0.0f, -0.19509032201612827f, -0.38268343236508978f, -0.55557023301960222f,
+                             -0.70710678118654757f, -0.83146961230254524f, -0.92387953251128674f, -0.98078528040323045f,
+                             -1.0f, -0.98078528040323045f, -0.92387953251128674f, -0.83146961230254524f,
+                             -0.70710678118654757f, -0.55557023301960222f, -0.38268343236508978f, -0.19509032201612827f,
+                             0.0f, 0.19509032201612827f, 0.38268343236508978f, 0.55557023301960222f,
+                             0.70710678118654757f, 0.83146961230254524f, 0.92387953251128674f, 0.98078528040323045f};
+    return c[e & 31];
 }
-constexpr float sin16(int e) { return cos16(e - 4); }
+constexpr float sin32(int e) { return cos32(e - 8); }
 
-// v * W_N^E with W_N = exp(-2 pi i / N), N dividing 16.
+// v * W_N^E with W_N = exp(-2 pi i / N), N dividing 32.
 template <int N, int E> __device__ __forceinline__ float2 twc(float2 v)
 {
-    constexpr int e = (E * (16 / N)) & 15;
+    constexpr int e = (E * (32 / N)) & 31;
     if constexpr (e == 0) {
         return v;
-    } else if constexpr (e == 4) {
-        return mul_mi(v);
     } else if constexpr (e == 8) {
+        return mul_mi(v);
+    } else if constexpr (e == 16) {
         return make_float2(-v.x, -v.y);
-    } else if constexpr (e == 12) {
+    } else if constexpr (e == 24) {
         return mul_pi(v);
     } else {
-        constexpr float c = cos16(e), s = sin16(e);
+        constexpr float c = cos32(e), s = sin32(e);
         return make_float2(__builtin_fmaf(v.x, c, v.y * s), __builtin_fmaf(v.y, c, -(v.x * s)));
     }
 }
@@ -104,6 +108,9 @@ template <> struct Dft<8> {
 };
 template <> struct Dft<16> {
     static __device__ __forceinline__ void run(float2 *v) { dft_ct<4, 4>(v); }
+};
+template <> struct Dft<32> {
+    static __device__ __forceinline__ void run(float2 *v) { dft_ct<4, 8>(v); }
 };
 
 // Synchronise the lanes of one FFT group between LDS passes.
@@ -436,7 +443,8 @@ template <int LOG2C> __device__ __forceinline__ void stage_twiddles_lds(float2 *
 }
 
 // Lanes per transform: C <= 1024 lives in one wave (or part of one); larger C
-// spans C/16 lanes over several waves.
+// spans several waves: 128 lanes of 16 elements at C = 2048, C/32 lanes of 32
+// elements (radix-32 passes) from C = 4096.
 template <int LOG2C> struct FftLanes {
     static constexpr int C = 1 << LOG2C;
     static constexpr int E = fft_elems_per_lane(LOG2C);

@@ -5,10 +5,12 @@
 namespace pfb {
 
 // Elements per lane for a C = 2^log2c point transform: 16 where the pass
-// radices come out even, 8 otherwise.
+// radices come out even, 8 otherwise, and 32 from C = 4096, where radix-32
+// passes need one LDS exchange fewer (C = 8192: 32 x 32 x 8 instead of
+// 16 x 16 x 16 x 2) and half as many waves meet at each barrier.
 constexpr int fft_elems_per_lane(int log2c)
 {
-    return (log2c == 5 || log2c == 6 || log2c == 7 || log2c == 9) ? 8 : 16;
+    return (log2c == 5 || log2c == 6 || log2c == 7 || log2c == 9) ? 8 : log2c >= 12 ? 32 : 16;
 }
 
 constexpr int fft_ilog2(int v) { return v <= 1 ? 0 : 1 + fft_ilog2(v / 2); }
