@@ -210,8 +210,9 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_bwd_kernel(BwdArgs a
         };
         // Across a round only the window rows that its transforms overwrite
         // stay in registers: the other half of the window is still in LDS
-        // (the previous round's rows) and is read back after the round, so
-        // those registers are free during the transforms. Before the first
+        // (the previous round's rows) and is read back once the round's
+        // transforms are done, before its barrier, so those registers are
+        // free during the transforms. Before the first
         // chunk the second-half LDS rows hold zeros (the window's
         // not-yet-walked rows).
         sfor<HALF>([&](auto r) PFB_INLINE {
