@@ -112,7 +112,7 @@ def cpu_baseline(B, S, C, T, seed):
     is B*S*C over the sum, on all threads."""
     import oracle
     from paper_1511_03599_amd import synth
-    fir_rows, dft_rows = 8192, 768
+    fir_rows, dft_rows = 16384, 3072  # about 10 s of host work in all
     st = synth.noise_stream(1, C, T, fir_rows, seed, fast=True)
     x = oracle._as_c128(st.x)
     h = st.h.astype("float64")
