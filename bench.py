@@ -488,7 +488,7 @@ def main():
 
     ws = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or ws > 1:
-        print("bench.py runs on one GPU: this filter bank is a single-GPU build (streams and beams "
+        print("bench.py runs on one GPU: the library runs each problem on one GPU (streams and beams "
               "would shard across GPUs with no communication); run it with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
