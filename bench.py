@@ -317,7 +317,7 @@ def extras_batched(dev, stream, tune=True):
     tuned_tile = None
     if tune:
         # the batched tile size from the tuner (pfb_tune_batched, which
-        # times 256 KiB - 4 MiB tiles), read by the plan created below
+        # times 64 KiB - 4 MiB tiles), read by the plan created below
         pfb.BatchedPlan.tune(desc, tune_cache())
         os.environ["PFB_TUNE_CACHE"] = tune_cache()
         tuned_tile = open(tune_cache()).read().strip().splitlines()[-1]

@@ -432,7 +432,7 @@ extern "C" pfb_status pfb_tune_batched(int32_t nbeams, const pfb_desc *beams, co
     }
     double best_t = -1.0;
     int best_kib = 0;
-    for (int kib : {256, 512, 1024, 2048, 4096}) {
+    for (int kib : {64, 128, 256, 512, 1024, 2048, 4096}) {
         batched_tile_set_override(kib);
         pfb_plan *p = nullptr;
         const pfb_status cs = pfb_plan_create_batched(nbeams, beams, &p);

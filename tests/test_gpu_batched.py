@@ -116,4 +116,4 @@ def test_batched_tuner_writes_cache(dev, tmp_path):
     f = lines[0].split()
     assert f[1] == "batched" and int(f[2]) == 2 and int(f[3]) == 1024 * 2000 + 256 * 4000
     kib = int(f[4].split("=")[1])
-    assert kib in (256, 512, 1024, 2048, 4096)
+    assert kib in (64, 128, 256, 512, 1024, 2048, 4096)
