@@ -32,7 +32,7 @@ def adjoint_kind_cache(tmp_path, monkeypatch, C, T, S, B, ws):
                                      (1024, 16, 700, 2), (256, 3, 530, 1), (512, 13, 257, 2),
                                      (384, 8, 50, 2), (3072, 4, 12, 1), (105, 16, 40, 1),
                                      (1024, 7, 300, 2), (1024, 2, 45, 1), (1024, 16, 1, 1), (1024, 4, 3, 2),
-                                     (512, 16, 1000, 1), (512, 5, 17, 3)])
+                                     (512, 16, 1000, 1), (512, 5, 17, 3), (2048, 8, 20, 1), (8192, 4, 6, 2)])
 @pytest.mark.parametrize("mode", ["default", "split", "single_role", "wave_specialised"])
 def test_backward_parity(dev, C, T, S, B, mode, tmp_path, monkeypatch):
     import torch
