@@ -327,15 +327,16 @@ static pfb_status plan_single(const pfb_desc *d, pfb_plan *p)
     // Two channels per lane (16-byte complex64 loads) where the doubled
     // register window fits (padded taps <= 16) and C is even; short tiles of
     // 32 filtered spectra keep many waves resident (the halo rows they re-read
-    // are served by the caches). For int8 input, tiles of 64 rows measured
-    // faster (4096 channels, 16 taps: 0.306 -> 0.280 ms with inputs beyond
-    // the last-level cache; the other input types were slower with 64).
+    // are served by the caches). For int8 input at 16 taps, tiles of 64 rows
+    // measured faster (4096 channels: 0.31 -> 0.27 ms with inputs beyond the
+    // last-level cache; at 8 taps 64 rows were slower, 0.25 -> 0.28 ms, and
+    // the other input types were slower with 64 too).
     // Longer windows re-read T-1 halo rows per tile, so their tiles are
     // longer: 128 rows at 32 taps (1024 channels: 0.25 -> 0.22 ms), 64 rows
     // at 64 taps (faster than 32 or 128).
     const bool cpt2_ok = p->tp <= 16 && d->channels % 2 == 0;
     p->fir_cpt = cpt2_ok ? 2 : 1;
-    p->fir_sb = p->tp >= 64 ? 64 : p->tp == 32 ? 128 : d->dtype == PFB_CI8 ? 64 : 32;
+    p->fir_sb = p->tp >= 64 ? 64 : p->tp == 32 ? 128 : (d->dtype == PFB_CI8 && p->tp == 16) ? 64 : 32;
     if (tuned) {
         if (te.fir_cpt == 1 || (te.fir_cpt == 2 && cpt2_ok))
             p->fir_cpt = te.fir_cpt;
