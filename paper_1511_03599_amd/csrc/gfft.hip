@@ -95,15 +95,18 @@ template <int G> __device__ __forceinline__ void gf_sync()
     }
 }
 
-template <int R, int G>
-__device__ __forceinline__ void gf_pass(const float2 *src, float2 *dst, int C, int L, const float2 *tw, int lane)
+// One pass: `src(idx)` returns input element idx, `dst(idx, v)` takes output
+// element idx (LDS rows between passes; the row in global memory for the
+// first pass's inputs and the last pass's outputs, both coalesced).
+template <int R, int G, class Src, class Dst>
+__device__ __forceinline__ void gf_pass(Src &&src, Dst &&dst, int C, int L, const float2 *tw, int lane)
 {
     const int CR = C / R;
     const int tstep = C / (R * L);
     for (int j = lane; j < CR; j += G) {
         const int k = j % L;
         float2 v[R];
-        sfor<R>([&](auto i) PFB_INLINE { v[i] = src[j + decltype(i)::value * CR]; });
+        sfor<R>([&](auto i) PFB_INLINE { v[i] = src(j + decltype(i)::value * CR); });
         if (L > 1) {
             sfor<R - 1>([&](auto ic) PFB_INLINE {
                 constexpr int i = decltype(ic)::value + 1;
@@ -112,7 +115,22 @@ __device__ __forceinline__ void gf_pass(const float2 *src, float2 *dst, int C, i
         }
         dft_any<R>(v);
         const int o = (j - k) * R + k;
-        sfor<R>([&](auto i) PFB_INLINE { dst[o + decltype(i)::value * L] = v[i]; });
+        sfor<R>([&](auto i) PFB_INLINE { dst(o + decltype(i)::value * L, v[i]); });
+    }
+}
+
+// Pass p of the schedule with radix R (runtime), from src to dst.
+template <int G, class Src, class Dst>
+__device__ __forceinline__ void gf_pass_any(int R, Src &&src, Dst &&dst, int C, int L, const float2 *tw, int lane)
+{
+    switch (R) {
+    case 16: gf_pass<16, G>(src, dst, C, L, tw, lane); break;
+    case 8: gf_pass<8, G>(src, dst, C, L, tw, lane); break;
+    case 4: gf_pass<4, G>(src, dst, C, L, tw, lane); break;
+    case 2: gf_pass<2, G>(src, dst, C, L, tw, lane); break;
+    case 7: gf_pass<7, G>(src, dst, C, L, tw, lane); break;
+    case 5: gf_pass<5, G>(src, dst, C, L, tw, lane); break;
+    default: gf_pass<3, G>(src, dst, C, L, tw, lane); break;
     }
 }
 
@@ -133,33 +151,26 @@ __global__ __launch_bounds__(256) void gfft_kernel(FftArgs a, GfftSched s)
     float2 *out = a.out + g * a.out_gstride + r * C;
     float2 *A = gf_lds + (size_t)grp * 2 * C;
     float2 *B = A + C;
-    for (int i = lane; i < C; i += G) {
-        const float2 v = in[i];
-        A[i] = INV ? conj2(v) : v;
-    }
+    auto lds_src = [&](const float2 *buf) { return [buf](int idx) { return buf[idx]; }; };
+    auto lds_dst = [&](float2 *buf) { return [buf](int idx, float2 v) { buf[idx] = v; }; };
+    // the first pass reads the row from global memory and the last writes it
+    // there (the schedule always has at least two passes: C >= 32, radix <= 16)
+    gf_pass_any<G>(
+        s.radix[0], [&](int idx) { const float2 v = in[idx]; return INV ? conj2(v) : v; }, lds_dst(A), C, 1, a.tw,
+        lane);
     gf_sync<G>();
-    int L = 1;
-    for (int p = 0; p < s.npass; ++p) {
-        const int R = s.radix[p];
-        switch (R) {
-        case 16: gf_pass<16, G>(A, B, C, L, a.tw, lane); break;
-        case 8: gf_pass<8, G>(A, B, C, L, a.tw, lane); break;
-        case 4: gf_pass<4, G>(A, B, C, L, a.tw, lane); break;
-        case 2: gf_pass<2, G>(A, B, C, L, a.tw, lane); break;
-        case 7: gf_pass<7, G>(A, B, C, L, a.tw, lane); break;
-        case 5: gf_pass<5, G>(A, B, C, L, a.tw, lane); break;
-        default: gf_pass<3, G>(A, B, C, L, a.tw, lane); break;
-        }
+    int L = s.radix[0];
+    for (int p = 1; p + 1 < s.npass; ++p) {
+        gf_pass_any<G>(s.radix[p], lds_src(A), lds_dst(B), C, L, a.tw, lane);
         float2 *t = A;
         A = B;
         B = t;
-        L *= R;
+        L *= s.radix[p];
         gf_sync<G>();
     }
-    for (int i = lane; i < C; i += G) {
-        const float2 v = A[i];
-        store_nt(out + i, INV ? conj2(v) : v);
-    }
+    gf_pass_any<G>(
+        s.radix[s.npass - 1], lds_src(A), [&](int idx, float2 v) { store_nt(out + idx, INV ? conj2(v) : v); }, C, L,
+        a.tw, lane);
 }
 
 // Radix schedule of a 7-smooth C (false if C has another prime factor or
@@ -177,7 +188,7 @@ bool gfft_schedule(int C, GfftSched *s)
             rem /= r;
         }
     }
-    if (rem != 1)
+    if (rem != 1 || np < 2) // the kernel's first and last passes are distinct
         return false;
     t.npass = np;
     t.group = C <= 2048 ? 64 : 256;
