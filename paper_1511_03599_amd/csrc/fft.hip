@@ -46,12 +46,24 @@ __global__ __launch_bounds__(FftKernelShape<LOG2C>::NT, FftKernelShape<LOG2C>::M
 // per spectrum, nsub sub-bands of C channels, each channel holding 2
 // interleaved polarisations). Row r = (s * nsub + sub) * 2 + pol transforms
 // the C elements at base + 2*idx, base = (s * nsub + sub) * 2C + pol, and
-// writes its bins to the same positions of out.
+// writes its bins to the same positions of out. A workgroup takes both
+// polarisations of a sub-band spectrum, so the two transforms that share
+// every 16-byte pair of the row read and write it from one CU (one
+// polarisation per workgroup left each line to two CUs, often on two XCDs:
+// 4096 channels, 8 sub-bands, int8, 16 taps 1.23 -> 0.92 ms).
+template <int LOG2C> struct FftPol2Shape {
+    using FL = FftLanes<LOG2C>;
+    static constexpr int G = FL::G;
+    static constexpr int NT = G > 64 ? 2 * G : 256; // threads per block
+    static constexpr int F = NT / G;                // rows per block: both polarisations together
+    static constexpr int MIN_WAVES = NT >= 512 ? 2 : 1;
+};
+
 template <int LOG2C, bool INV>
-__global__ __launch_bounds__(FftKernelShape<LOG2C>::NT, FftKernelShape<LOG2C>::MIN_WAVES) void fft_pol2_kernel(
+__global__ __launch_bounds__(FftPol2Shape<LOG2C>::NT, FftPol2Shape<LOG2C>::MIN_WAVES) void fft_pol2_kernel(
     FftArgs a)
 {
-    using K = FftKernelShape<LOG2C>;
+    using K = FftPol2Shape<LOG2C>;
     constexpr int G = K::G;
     constexpr int C = 1 << LOG2C;
     using S = FftShape<LOG2C, G>;
@@ -59,6 +71,8 @@ __global__ __launch_bounds__(FftKernelShape<LOG2C>::NT, FftKernelShape<LOG2C>::M
     const int gid = (int)threadIdx.x / G;
     const int lane = (int)threadIdx.x % G;
     const int64_t row = (int64_t)blockIdx.x * K::F + gid;
+    // rows come in polarisation pairs and a block holds whole pairs, so with
+    // G > 64 (block barriers) both groups of a block are in range
     if (row >= a.nrows)
         return;
     const int64_t base = (row >> 1) * 2 * C + (row & 1);
@@ -74,7 +88,7 @@ hipError_t launch_fft_pol2(const FftArgs &a, int log2c, hipStream_t st)
     switch (log2c) {
 #define PFB_POL2_C(L2)                                                                                       \
     case L2: {                                                                                               \
-        using K = FftKernelShape<L2>;                                                                        \
+        using K = FftPol2Shape<L2>;                                                                          \
         const int64_t blocks = (a.nrows + K::F - 1) / K::F;                                                  \
         if (blocks <= 0)                                                                                     \
             return hipSuccess;                                                                               \
