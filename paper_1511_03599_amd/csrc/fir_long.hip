@@ -26,7 +26,8 @@ __global__ __launch_bounds__(256, fir_long_waves(DT)) void fir_long_kernel(FirAr
     constexpr int SEG = 32; // taps per segment = window rows
     constexpr int R = 32;   // filtered spectra per tile
     constexpr int D = 4;    // prefetch depth (rows): the 2T FMA per output hide the rest
-    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave_id();
+    // scalar task index: tile, row and address bases stay in scalar registers
+    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave_id_uniform();
     const int64_t total = (int64_t)a.B * a.n_tiles * a.n_cchunks;
     if (gw >= total)
         return;
@@ -50,6 +51,13 @@ __global__ __launch_bounds__(256, fir_long_waves(DT)) void fir_long_kernel(FirAr
     float2 acc[R];
     sfor<R>([&](auto o) PFB_INLINE { acc[o] = make_float2(0.0f, 0.0f); });
     const int nseg = (a.T + SEG - 1) / SEG;
+    // Wave-uniform: a whole tile, every lane on a channel and every row that
+    // any segment's window reads inside the stream. Such tiles issue every
+    // load unconditionally, so the compiler waits only for the row that
+    // enters the window (a load under a branch makes it wait for all).
+    const bool clean = (cch + 1) * 64 <= a.C && nout == R && s_begin >= 0 &&
+                       s_begin + (int64_t)nseg * SEG + R - 2 < a.in_rows;
+    auto ld_clean = [&](int64_t row, Packed<DT, 1> &o) { load_packed<DT, 1>(xb, row * a.C + c0, o); };
 #pragma unroll 1
     for (int g = 0; g < nseg; ++g) {
         float hp[SEG];
@@ -62,6 +70,28 @@ __global__ __launch_bounds__(256, fir_long_waves(DT)) void fir_long_kernel(FirAr
         const int64_t r0 = s_begin + (int64_t)g * SEG;
         float2 w[SEG][1];
         Packed<DT, 1> pf[D];
+        if (clean) {
+            sfor<SEG - 1>([&](auto j) PFB_INLINE {
+                Packed<DT, 1> t;
+                ld_clean(r0 + j, t);
+                unpack<DT, 1>(t, w[j]);
+            });
+            sfor<D>([&](auto k) PFB_INLINE { ld_clean(r0 + SEG - 1 + k, pf[k]); });
+            sfor<R>([&](auto oc) PFB_INLINE {
+                constexpr int o = decltype(oc)::value;
+                unpack<DT, 1>(pf[o % D], w[(o + SEG - 1) % SEG]);
+                if constexpr (o + D < R)
+                    ld_clean(r0 + o + SEG - 1 + D, pf[o % D]);
+                float ar = acc[o].x, ai = acc[o].y;
+                sfor<SEG>([&](auto jc) PFB_INLINE {
+                    constexpr int j = decltype(jc)::value;
+                    ar = __builtin_fmaf(hp[j], w[(o + j) % SEG][0].x, ar);
+                    ai = __builtin_fmaf(hp[j], w[(o + j) % SEG][0].y, ai);
+                });
+                acc[o] = make_float2(ar, ai);
+            });
+            continue;
+        }
         sfor<SEG - 1>([&](auto j) PFB_INLINE {
             Packed<DT, 1> t;
             ld(r0 + j, t);
