@@ -88,10 +88,14 @@ __device__ __forceinline__ void fir_wave_task(const FirArgs &a, int64_t gw)
             return w[slot][k];
     };
     Packed<DT, CPT> pf[D]; // prefetched rows, still packed
-    // TP > 16: a whole tile of U rows, every row it reads inside the stream
-    // and every lane on a channel (wave-uniform)
-    const bool tp_clean = TP > 16 && (cch + 1) * 64 * CPT <= a.C && nout == U && row0 >= 0 &&
-                          row0 + nout + TP - 2 < a.in_rows;
+    // TP > 16: a tile of one U-row block (MULTI: of whole U-row blocks),
+    // every row it reads inside the stream and every lane on a channel
+    // (wave-uniform). MULTI only where the loop over blocks still fits the
+    // registers without spilling (32 taps, 8-byte complex64 or 4-byte fp16
+    // samples, the stand-alone FIR kernel).
+    constexpr bool MULTI = TP == 32 && NT && (DT == DT_C64 || DT == DT_CF16);
+    const bool tp_clean = TP > 16 && (cch + 1) * 64 * CPT <= a.C && (nout == U || (MULTI && nout > 0 && nout % U == 0)) &&
+                          row0 >= 0 && row0 + nout + TP - 2 < a.in_rows;
     sfor<TP - 1>([&](auto j) PFB_INLINE {
         Packed<DT, CPT> t;
         if constexpr (TP <= 16) {
@@ -185,15 +189,19 @@ __device__ __forceinline__ void fir_wave_task(const FirArgs &a, int64_t gw)
         for (; base < nout; base += U)
             block(base, std::integral_constant<int, TAIL>{});
     } else if (tp_clean) {
-        // Windows of 32 taps and more, a whole tile of U rows inside the
-        // stream with every lane on a channel (the common case): one block
-        // with every load issued unconditionally, so the compiler waits only
-        // for the row that enters the window and D rows stay in flight.
-        sfor<U>([&](auto jjc) PFB_INLINE {
+        // Windows of 32 taps and more, a tile of whole U-row blocks inside
+        // the stream with every lane on a channel (the common case): every
+        // load is issued unconditionally, so the compiler waits only for the
+        // row that enters the window and D rows stay in flight. Blocks before
+        // the last prefetch the next block's first rows; the last block
+        // prefetches only inside itself.
+        auto clean_block = [&](int base, auto lastc) PFB_INLINE {
+            constexpr bool LASTB = decltype(lastc)::value;
+            sfor<U>([&](auto jjc) PFB_INLINE {
             constexpr int jj = decltype(jjc)::value;
-            const int64_t row_in = row0 + jj + TP - 1;
+            const int64_t row_in = row0 + base + jj + TP - 1;
             unpack<DT, CPT>(pf[jj % D], w[(jj + TP - 1) % TP]);
-            if constexpr (jj + D < U)
+            if constexpr (!LASTB || jj + D < U)
                 load_packed<DT, CPT>(xb, (row_in + D) * a.C + c0, pf[jj % D]);
             float2 acc[CPT];
             sfor<CPT>([&](auto k) PFB_INLINE {
@@ -206,10 +214,17 @@ __device__ __forceinline__ void fir_wave_task(const FirArgs &a, int64_t gw)
                 acc[k] = make_float2(ar, ai);
             });
             if constexpr (NT)
-                store_c64_nt<CPT>(yb + (int64_t)jj * a.C, acc);
+                store_c64_nt<CPT>(yb + (int64_t)(base + jj) * a.C, acc);
             else
-                store_c64<CPT>(yb + (int64_t)jj * a.C, acc);
-        });
+                store_c64<CPT>(yb + (int64_t)(base + jj) * a.C, acc);
+            });
+        };
+        int base = 0;
+        if constexpr (MULTI) {
+            for (; base + U < nout; base += U)
+                clean_block(base, std::false_type{});
+        }
+        clean_block(base, std::true_type{});
     } else {
         // Windows of 32 taps and more, anything else (ragged tiles, stream
         // edges, the last partial channel chunk): one compact loop; rows
