@@ -17,7 +17,16 @@ the low-precision inputs at C=4096 with their errors against FP64, the
 64-beam batched launch against 64 separate plain launches, and the layouts
 of the later rows (streaming, non-power-of-two channel counts, sub-bands).
 
+Before timing the 64-beam launch it runs the library's batched tuner
+(pfb_tune_batched) and uses its tile size; `--tune all` also tunes the
+headline plan, `--tune none` uses built-in choices throughout. `--only`
+runs one extra alone (for profiling) and `--copy-calibration` ends with
+three plain 512 MiB device copies whose counter readings calibrate the
+FETCH_SIZE / WRITE_SIZE summaries under profiles/.
+
     python bench.py [--steps K] [--warmup W] [--no-cpu] [--quick]
+                    [--tune none|batched|all] [--only precision|sweep|batched]
+                    [--copy-calibration]
 """
 from __future__ import annotations
 
