@@ -1,0 +1,104 @@
+"""GPU parity of the large transforms over many rows: the split-path filter
+bank forward and adjoint at 2048 to 8192 channels, with enough spectra that
+each persistent transform workgroup (4096 and 8192 channels) takes several
+rows, and the sub-band layout at 4096 channels over many sub-band spectra.
+Rows are sampled where a workgroup's row sequence starts and steps
+(multiples of 512, 1024 and 2048 and their neighbours), at both ends of the
+streams and at seeded positions, and compared with the oracle (Algorithm 1
+then Eq. (2), and its adjoint restricted to those rows and channels).
+
+Inputs come from the seeded generators only; each case prints its name
+before it runs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1511_03599_amd import synth
+from helpers import GH_TOL, GX_TOL, SPEC_TOL, c128, rel_l2, say, taps_to_device, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+def sample_rows(n, seed, count):
+    rows = {0, 1, n - 2, n - 1}
+    for m in (512, 1024, 2048):
+        for k in (1, 2, 3):
+            rows.update((k * m - 1, k * m, k * m + 1))
+    g = synth.rng(seed)
+    rows = sorted(r for r in rows if 0 <= r < n)
+    extra = set()
+    while len(extra) < count:
+        extra.add(int(g.integers(0, n)))
+    return sorted(set(rows) | extra)
+
+
+@pytest.mark.parametrize("C,T,S,B", [(2048, 16, 4133, 1), (4096, 16, 2093, 1), (8192, 8, 1100, 2)])
+def test_many_row_split_forward(dev, C, T, S, B):
+    import torch
+    from paper_1511_03599_amd import pfb
+    say(f"many-row split forward C={C} T={T} S={S} B={B}")
+    st = synth.noise_stream(B, C, T, S, 2300 + C, fast=True)
+    xd = to_device(st.x, dev)
+    hd = taps_to_device(st.h, dev)
+    plan = pfb.Plan(C, T, S, B, "c64")
+    assert plan.info()["path"] != "fused"
+    Y = plan.execute(xd, hd)
+    torch.cuda.synchronize()
+    rows = sample_rows(S, 2301 + C, 4)
+    Yh = Y[:, rows].cpu().numpy()
+    for b in range(B):
+        for j, s in enumerate(rows):
+            want = oracle.pfb_forward(st.x[b:b + 1, s:s + T], st.h)[0, 0]
+            assert rel_l2(Yh[b, j].astype(np.complex128), want) <= SPEC_TOL, (b, s)
+
+
+def test_many_row_split_adjoint(dev):
+    import torch
+    from paper_1511_03599_amd import pfb
+    C, T, S = 4096, 16, 2093
+    say(f"many-row split adjoint C={C} T={T} S={S}")
+    st = synth.noise_stream(1, C, T, S, 2400, fast=True)
+    gYs = synth.complex_gaussian_c64((1, S, C), 2401)
+    xd = to_device(st.x, dev)
+    hd = taps_to_device(st.h, dev)
+    plan = pfb.Plan(C, T, S, 1, "c64")
+    assert plan.info()["backward_kind"] == "split"
+    gx, gh = plan.backward(xd, hd, torch.from_numpy(gYs).to(dev))
+    torch.cuda.synchronize()
+    # sample gradient rows: each needs T inverse-transformed gradient rows
+    rows = [0, 1023, 1024, 2047, 2048, S + T - 2]
+    gx_r = oracle.pfb_adjoint_x_rows(st.h, gYs, rows)
+    e = rel_l2(c128(gx[0, rows]), gx_r[0])
+    say(f"  gx rel L2 {e:.2e}")
+    assert e <= GX_TOL
+    # tap gradient, every tap of a few channels (each reduces over all rows)
+    ch = [0, 1, 2047, 4095]
+    gh_r = oracle.pfb_adjoint_h_channels(st.x, gYs, T, ch)
+    e = rel_l2(gh[:, ch].cpu().numpy().astype(np.float64), gh_r)
+    say(f"  gh rel L2 {e:.2e}")
+    assert e <= GH_TOL
+
+
+def test_many_unit_subbands(dev):
+    import torch
+    from paper_1511_03599_amd import pfb
+    CV, NS, T, S = 4096, 8, 16, 150
+    say(f"many-unit sub-band layout C_V={CV} N_sub={NS} T={T} S={S} ci8")
+    rows = S + T - 1
+    st = synth.noise_stream(1, NS * CV * 2, 1, rows, 2500, dtype="ci8")
+    xs = st.x[0].reshape(rows, NS, CV, 2, 2)           # [rows][sub][chan][pol][re,im]
+    h = synth.random_taps(CV, T, 2501)
+    plan = pfb.VegasPlan(CV, NS, T, S, "ci8")
+    Y = plan.execute(torch.from_numpy(np.ascontiguousarray(xs)).to(dev), taps_to_device(h, dev))
+    torch.cuda.synchronize()
+    # both ends of the stream and spectra on both sides of multiples of 64
+    # (512 sub-band transforms)
+    spectra = sorted({0, 63, 64, 127, 128, S - 1})
+    Yh = Y[spectra].cpu().numpy()                     # [spectra][sub][k][pol]
+    for sub in range(NS):
+        for pol in range(2):
+            xb = np.ascontiguousarray(xs[:, sub, :, pol, :])[None]
+            for j, s in enumerate(spectra):
+                want = oracle.pfb_forward(xb[:, s:s + T], h)[0, 0]
+                assert rel_l2(Yh[j, sub, :, pol].astype(np.complex128), want) <= SPEC_TOL, (sub, pol, s)
