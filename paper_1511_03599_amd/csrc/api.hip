@@ -534,6 +534,7 @@ static hipError_t run_fft(const pfb_plan *p, const float2 *in, float2 *out, int6
     a.rows_per_group = rows_per_group;
     a.in_gstride = in_gstride;
     a.out_gstride = out_gstride;
+    a.num_cus = p->num_cus;
     if (p->mixed)
         return launch_gfft(a, p->gf, inv, st);
     return launch_fft(a, p->log2c, inv, st);

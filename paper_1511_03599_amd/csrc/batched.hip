@@ -131,6 +131,29 @@ __device__ __forceinline__ void batched_fft(const float2 *tw, const float2 *slot
     static_assert(F * S::PADDED <= BT_LDS, "LDS");
     const int gid = (int)threadIdx.x / G;
     const int lane = (int)threadIdx.x % G;
+    if constexpr (G > 64) {
+        // Transforms span several waves and synchronise the block, so every
+        // group runs the passes (a group past the last row repeats the last
+        // row without storing it). The twiddles depend on the lane only:
+        // loaded once for all rounds of the tile.
+        FftResidentTwiddles<LOG2C, G> twr;
+        twr.load(lane, tw);
+        for (int base = 0; base < nrows; base += F) {
+            const int r = base + gid;
+            const bool valid = r < nrows;
+            const int rr = valid ? r : nrows - 1;
+            const float2 *in = slot + (int64_t)rr * C;
+            float2 *o = out + (int64_t)rr * C;
+            float2 v[S::E];
+            fft_gather_first<LOG2C, G, false>(lane, [&](int idx) { return in[idx]; }, v);
+            fft_passes_resident<LOG2C, G, false, false>(lane, lds + gid * S::PADDED, twr, v, [&](int idx, float2 t) {
+                if (valid)
+                    store_nt(o + idx, t);
+            });
+            lds_barrier(); // the LDS rows are reused by the next round
+        }
+        return;
+    }
     for (int base = 0; base < nrows; base += F) {
         const int r = base + gid;
         const bool valid = r < nrows;
@@ -138,19 +161,7 @@ __device__ __forceinline__ void batched_fft(const float2 *tw, const float2 *slot
         const int rr = valid ? r : nrows - 1;
         const float2 *in = slot + (int64_t)rr * C;
         float2 *o = out + (int64_t)rr * C;
-        if constexpr (F == 1) {
-            fft_run<LOG2C, G, false, false>(
-                lane, lds, tw, [&](int idx) { return in[idx]; }, [&](int idx, float2 v) { store_nt(o + idx, v); });
-        } else if constexpr (G > 64) {
-            // transforms span several waves and synchronise the block, so
-            // every group runs the passes
-            fft_run<LOG2C, G, false, false>(
-                lane, lds + gid * S::PADDED, tw, [&](int idx) { return in[idx]; },
-                [&](int idx, float2 v) {
-                    if (valid)
-                        store_nt(o + idx, v);
-                });
-        } else if (valid) {
+        if (valid) {
             fft_run<LOG2C, G, false, false>(
                 lane, lds + gid * S::PADDED, tw, [&](int idx) { return in[idx]; },
                 [&](int idx, float2 v) { store_nt(o + idx, v); });

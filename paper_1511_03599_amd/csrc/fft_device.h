@@ -407,6 +407,43 @@ __device__ __forceinline__ void fft_passes(int lane, float2 *lds, const float2 *
     }
 }
 
+// The twiddles of every pass P > 0 that this lane applies (those
+// fft_load_twiddles reads), for callers that keep them in registers across
+// many transforms: they depend on the lane index only (k = j mod L for the
+// lane's butterflies j), never on the row.
+template <int LOG2C, int G> struct FftResidentTwiddles {
+    using S = FftShape<LOG2C, G>;
+    static_assert(S::NPASS >= 2, "a one-pass transform has no twiddles");
+    float4 w[S::NPASS - 1][S::E / 2];
+    __device__ __forceinline__ void load(int lane, const float2 *tw)
+    {
+        const float2 *twp = as_global(tw);
+        sfor<S::NPASS - 1>([&](auto pp) PFB_INLINE {
+            fft_load_twiddles<LOG2C, G, decltype(pp)::value + 1>(lane, twp, w[decltype(pp)::value]);
+        });
+    }
+};
+
+// fft_passes with the twiddles already in registers (same arithmetic, in
+// the same order: same bits). SYNC_FIRST: lanes of the group may still be
+// reading the LDS row (the previous transform's last pass), so synchronise
+// before the first pass overwrites it.
+template <int LOG2C, int G, bool INV, bool SYNC_FIRST, class Dst>
+__device__ __forceinline__ void fft_passes_resident(int lane, float2 *lds, const FftResidentTwiddles<LOG2C, G> &tw,
+                                                    float2 (&v)[FftShape<LOG2C, G>::E], Dst &&dst)
+{
+    constexpr int NP = FftShape<LOG2C, G>::NPASS;
+    sfor<NP>([&](auto pp) PFB_INLINE {
+        constexpr int P = decltype(pp)::value;
+        if constexpr (P > 0)
+            fft_pass_gather<LOG2C, G, P>(lane, lds, v);
+        // every lane has read before any lane overwrites
+        if constexpr (G > 64 && P < NP - 1 && (P > 0 || SYNC_FIRST))
+            group_sync<G>();
+        fft_pass_compute<LOG2C, G, INV, false, P, Dst &, true>(lane, lds, nullptr, v, dst, tw.w[P > 0 ? P - 1 : 0]);
+    });
+}
+
 // Run one transform. `src(idx)` returns input element idx (first pass);
 // `dst(idx, v)` receives output element idx (last pass). When SRC_IN_LDS the
 // first pass reads this group's own LDS row. INV selects exp(+...).

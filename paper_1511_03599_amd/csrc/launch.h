@@ -40,11 +40,12 @@ struct GhArgs {
 struct FftArgs {
     const float2 *in;
     float2 *out;
-    const float2 *tw;    // C twiddles exp(-2 pi i n / C)
+    const float2 *tw;    // twiddle table of the C-point schedule (fft_device.h)
     int64_t nrows;
     int64_t rows_per_group;
     int64_t in_gstride;
     int64_t out_gstride;
+    int num_cus = 0;     // compute units of the device (sizes persistent grids; 0: one block per row)
 };
 
 // Fused FIR + FFT: one workgroup holds all C channels of a tile of S_B
