@@ -145,7 +145,7 @@ __device__ __forceinline__ void batched_fft(const float2 *tw, const float2 *slot
             const float2 *in = slot + (int64_t)rr * C;
             float2 *o = out + (int64_t)rr * C;
             float2 v[S::E];
-            fft_gather_first<LOG2C, G, false>(lane, [&](int idx) { return in[idx]; }, v);
+            fft_gather_first<LOG2C, G>(lane, [&](int idx) { return in[idx]; }, v);
             fft_passes_resident<LOG2C, G, false, false>(lane, lds + gid * S::PADDED, twr, v, [&](int idx, float2 t) {
                 if (valid)
                     store_nt(o + idx, t);

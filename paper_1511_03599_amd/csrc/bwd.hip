@@ -133,7 +133,7 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_bwd_kernel(BwdArgs a
         const int64_t q = q0 + base_ + r;
         if (base_ < nq && q >= 0 && q < a.S && base_ + r < nq) {
             const float2 *src = gYb + q * C;
-            fft_gather_first<LOG2C, G, true>(lane, [&](int idx) { return src[idx]; }, gv);
+            fft_gather_first<LOG2C, G>(lane, [&](int idx) { return src[idx]; }, gv);
         } else {
             sfor<E>([&](auto e) PFB_INLINE { gv[e] = make_float2(0.0f, 0.0f); });
         }
@@ -168,7 +168,7 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_bwd_kernel(BwdArgs a
             // registers across the loop
             int l8 = lane * 8;
             asm volatile("" : "+v"(l8));
-            fft_gather_first<LOG2C, G, true>(
+            fft_gather_first<LOG2C, G>(
                 lane,
                 [&](int idx) {
                     float2 o[1];
@@ -234,8 +234,7 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_bwd_kernel(BwdArgs a
                 // loop and held in registers for both rounds
                 int ln = lane;
                 asm volatile("" : "+v"(ln));
-                fft_passes<LOG2C, G, true, false, true>(ln, row, tws, cur,
-                                                        [&](int idx, float2 v) { row[S::pad(idx)] = v; });
+                fft_passes<LOG2C, G, true, false, true>(ln, row, tws, cur, LdsRowDst{row});
                 // window slots holding rows of the half this round did not
                 // overwrite (the last min(TP, HALF) rows of that half). They
                 // are read back before this round's barrier: those rows were
@@ -277,8 +276,7 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_bwd_kernel(BwdArgs a
                 sfor<E>([&](auto e) PFB_INLINE { cur[e] = gv[e]; });
             }
             float2 *row = lds + (round * F::NG + gid) * S::PADDED;
-            fft_passes<LOG2C, G, true, false, true>(lane, row, tws, cur,
-                                                    [&](int idx, float2 v) { row[S::pad(idx)] = v; });
+            fft_passes<LOG2C, G, true, false, true>(lane, row, tws, cur, LdsRowDst{row});
         }
         lds_barrier();
         // 2. sample gradient and tap-gradient partials. In FULL chunks (every

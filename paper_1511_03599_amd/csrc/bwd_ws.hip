@@ -101,7 +101,7 @@ __global__ __launch_bounds__((WsShape<LOG2C, TP>::NT)) void fused_bwd_ws_kernel(
             const int64_t q = q0 + (int64_t)k * RB + r;
             if (q >= 0 && q < a.S) {
                 const float2 *src = gYb + q * C;
-                fft_gather_first<LOG2C, G, true>(lane, [&](int idx) { return src[idx]; }, v);
+                fft_gather_first<LOG2C, G>(lane, [&](int idx) { return src[idx]; }, v);
             } else {
                 sfor<E>([&](auto e) PFB_INLINE { v[e] = make_float2(0.0f, 0.0f); });
             }
@@ -130,8 +130,7 @@ __global__ __launch_bounds__((WsShape<LOG2C, TP>::NT)) void fused_bwd_ws_kernel(
                 if (k + 1 < nchunks)
                     issue(k + 1);
                 float2 *row = gy_buf + (buf * RB + r) * PADDED;
-                fft_passes<LOG2C, G, true, false, false, false>(lane, row, a.tw, v,
-                                                  [&](int idx, float2 t) { row[S::pad(idx)] = t; });
+                fft_passes<LOG2C, G, true, false, false, false>(lane, row, a.tw, v, LdsRowDst{row});
             };
             issue(0);
             finish(0, 0);
@@ -162,8 +161,7 @@ __global__ __launch_bounds__((WsShape<LOG2C, TP>::NT)) void fused_bwd_ws_kernel(
                     });
                 }
                 float2 *row = gy_buf + (buf * RB + r) * PADDED;
-                fft_passes<LOG2C, G, true, false, false, false>(lane, row, a.tw, v,
-                                                  [&](int idx, float2 t) { row[S::pad(idx)] = t; });
+                fft_passes<LOG2C, G, true, false, false, false>(lane, row, a.tw, v, LdsRowDst{row});
                 if (want_gh) {
                     sfor<W::XQ - XH>([&](auto ec) PFB_INLINE {
                         constexpr int e = decltype(ec)::value;

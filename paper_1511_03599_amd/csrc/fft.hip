@@ -83,7 +83,7 @@ __global__ __launch_bounds__(FftPersistShape<LOG2C>::NT, FftPersistShape<LOG2C>:
         const float2 *in = a.in + g * a.in_gstride + r * C;
         float2 *out = a.out + g * a.out_gstride + r * C;
         float2 v[S::E];
-        fft_gather_first<LOG2C, G, INV>(lane, [&](int idx) { return in[idx]; }, v);
+        fft_gather_first<LOG2C, G>(lane, [&](int idx) { return in[idx]; }, v);
         fft_passes_resident<LOG2C, G, INV, true>(lane, lds, tw, v,
                                                  [&](int idx, float2 t) { store_nt(out + idx, t); });
     }

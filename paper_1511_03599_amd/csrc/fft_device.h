@@ -3,7 +3,11 @@
 //
 // The transform is the DFT of Sec. 2, Eq. (2): unnormalised, bins in natural
 // order, exp(-2 pi i n m / C). The inverse (exp(+...), unnormalised) is the
-// same network applied to conjugated input with conjugated output.
+// same network with every constant and twiddle conjugated. Negation is
+// exact and every operation here rounds symmetrically, so this gives the
+// values of the conjugate-in, conjugate-out form of the forward network
+// (up to the sign of an exact zero) without flipping the signs of the input
+// and output elements.
 //
 // Each pass of radix R with stride L (the product of the radices of earlier
 // passes) lets every butterfly j (0 <= j < C/R) read elements j + i*C/R,
@@ -21,6 +25,8 @@
 // [pass_offset(P) + k*R + i], so the R twiddles of one butterfly are
 // contiguous and load as R/2 aligned 16-byte vectors.
 #pragma once
+
+#include <type_traits>
 
 #include "device_common.h"
 #include "fft_schedule.h"
@@ -60,11 +66,12 @@ template <int N, int E> __device__ __forceinline__ float2 twc(float2 v)
     }
 }
 
-template <int R> struct Dft;
-template <> struct Dft<1> {
+// R-point DFT in registers; INV: exp(+...) (conjugated constants).
+template <int R, bool INV = false> struct Dft;
+template <bool INV> struct Dft<1, INV> {
     static __device__ __forceinline__ void run(float2 *) {}
 };
-template <> struct Dft<2> {
+template <bool INV> struct Dft<2, INV> {
     static __device__ __forceinline__ void run(float2 *v)
     {
         float2 a = v[0], b = v[1];
@@ -72,11 +79,12 @@ template <> struct Dft<2> {
         v[1] = csub(a, b);
     }
 };
-template <> struct Dft<4> {
+template <bool INV> struct Dft<4, INV> {
     static __device__ __forceinline__ void run(float2 *v)
     {
+        const float2 d = csub(v[1], v[3]);
         float2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
-        float2 t2 = cadd(v[1], v[3]), t3 = mul_mi(csub(v[1], v[3]));
+        float2 t2 = cadd(v[1], v[3]), t3 = INV ? mul_pi(d) : mul_mi(d);
         v[0] = cadd(t0, t2);
         v[2] = csub(t0, t2);
         v[1] = cadd(t1, t3);
@@ -85,32 +93,48 @@ template <> struct Dft<4> {
 };
 
 // R = N1 * N2 by one Cooley-Tukey step: n = N2 n1 + n2, k = k1 + N1 k2.
-template <int N1, int N2> __device__ __forceinline__ void dft_ct(float2 *v)
+// INV multiplies by W_N^{-e} = W_N^{N-e}.
+template <int N1, int N2, bool INV = false> __device__ __forceinline__ void dft_ct(float2 *v)
 {
     constexpr int N = N1 * N2;
     float2 a[N2][N1];
     sfor<N2>([&](auto n2) PFB_INLINE {
         sfor<N1>([&](auto n1) PFB_INLINE { a[n2][n1] = v[N2 * n1 + n2]; });
-        Dft<N1>::run(a[n2]);
+        Dft<N1, INV>::run(a[n2]);
         sfor<N1>([&](auto k1) PFB_INLINE {
-            a[n2][k1] = twc<N, decltype(n2)::value * decltype(k1)::value>(a[n2][k1]);
+            constexpr int e = (decltype(n2)::value * decltype(k1)::value) % N;
+            a[n2][k1] = twc<N, INV ? (N - e) % N : e>(a[n2][k1]);
         });
     });
     sfor<N1>([&](auto k1) PFB_INLINE {
         float2 b[N2];
         sfor<N2>([&](auto n2) PFB_INLINE { b[n2] = a[n2][k1]; });
-        Dft<N2>::run(b);
+        Dft<N2, INV>::run(b);
         sfor<N2>([&](auto k2) PFB_INLINE { v[k1 + N1 * k2] = b[k2]; });
     });
 }
-template <> struct Dft<8> {
-    static __device__ __forceinline__ void run(float2 *v) { dft_ct<4, 2>(v); }
+template <bool INV> struct Dft<8, INV> {
+    static __device__ __forceinline__ void run(float2 *v) { dft_ct<4, 2, INV>(v); }
 };
-template <> struct Dft<16> {
-    static __device__ __forceinline__ void run(float2 *v) { dft_ct<4, 4>(v); }
+template <bool INV> struct Dft<16, INV> {
+    static __device__ __forceinline__ void run(float2 *v) { dft_ct<4, 4, INV>(v); }
 };
-template <> struct Dft<32> {
-    static __device__ __forceinline__ void run(float2 *v) { dft_ct<4, 8>(v); }
+template <bool INV> struct Dft<32, INV> {
+    static __device__ __forceinline__ void run(float2 *v) { dft_ct<4, 8, INV>(v); }
+};
+
+// v * w, or v * conj(w) for the inverse transform
+template <bool INV> __device__ __forceinline__ float2 cmul_tw(float2 v, float2 w)
+{
+    return cmul(v, INV ? conj2(w) : w);
+}
+
+// A destination that is a padded LDS row: output element idx goes to
+// row[pad(idx)]. The last pass forms each butterfly's padded address once
+// and adds constants (a generic `dst(idx, v)` recomputes pad(idx) per
+// element).
+struct LdsRowDst {
+    float2 *row;
 };
 
 // Synchronise the lanes of one FFT group between LDS passes.
@@ -156,7 +180,7 @@ template <int LOG2C, int G> struct FftShape {
 // the order the first pass consumes them: element j + i*C/R of butterfly
 // j = lane + G*q goes to v[q*R + i]. Split from the passes so that a caller
 // can issue these loads early and overlap their latency with other work.
-template <int LOG2C, int G, bool INV, class Src>
+template <int LOG2C, int G, class Src>
 __device__ __forceinline__ void fft_gather_first(int lane, Src &&src, float2 (&v)[FftShape<LOG2C, G>::E])
 {
     using S = FftShape<LOG2C, G>;
@@ -165,12 +189,7 @@ __device__ __forceinline__ void fft_gather_first(int lane, Src &&src, float2 (&v
     constexpr int CR = S::C / R;
     sfor<NB>([&](auto q) PFB_INLINE {
         const int j = lane + G * decltype(q)::value;
-        sfor<R>([&](auto i) PFB_INLINE {
-            float2 t = src(j + decltype(i)::value * CR);
-            if constexpr (INV)
-                t = conj2(t);
-            v[decltype(q)::value * R + decltype(i)::value] = t;
-        });
+        sfor<R>([&](auto i) PFB_INLINE { v[decltype(q)::value * R + decltype(i)::value] = src(j + decltype(i)::value * CR); });
     });
 }
 
@@ -200,7 +219,7 @@ template <bool TW_LDS> __device__ __forceinline__ const float2 *fft_twiddle_base
 // sits at pad(j) + i*(C/R + C/R/16) because C/R is a multiple of 16, so each
 // butterfly needs one address and constant offsets (no per-element index
 // arithmetic).
-template <int LOG2C, int G, bool INV>
+template <int LOG2C, int G>
 __device__ __forceinline__ void fft_gather_first_lds(int lane, const float2 *row, float2 (&v)[FftShape<LOG2C, G>::E])
 {
     using S = FftShape<LOG2C, G>;
@@ -212,10 +231,7 @@ __device__ __forceinline__ void fft_gather_first_lds(int lane, const float2 *row
     sfor<NB>([&](auto q) PFB_INLINE {
         const int pj = pl + decltype(q)::value * (G + G / 16);
         sfor<R>([&](auto i) PFB_INLINE {
-            float2 t = row[pj + decltype(i)::value * (CR + CR / 16)];
-            if constexpr (INV)
-                t = conj2(t);
-            v[decltype(q)::value * R + decltype(i)::value] = t;
+            v[decltype(q)::value * R + decltype(i)::value] = row[pj + decltype(i)::value * (CR + CR / 16)];
         });
     });
 }
@@ -300,15 +316,15 @@ __device__ __forceinline__ void fft_pass_compute(int lane, float2 *lds, const fl
                 constexpr int H = decltype(hh)::value;
                 const float4 w2 = wpre[Q * (R / 2) + H];
                 if constexpr (H > 0)
-                    v[Q * R + 2 * H] = cmul(v[Q * R + 2 * H], make_float2(w2.x, w2.y));
-                v[Q * R + 2 * H + 1] = cmul(v[Q * R + 2 * H + 1], make_float2(w2.z, w2.w));
+                    v[Q * R + 2 * H] = cmul_tw<INV>(v[Q * R + 2 * H], make_float2(w2.x, w2.y));
+                v[Q * R + 2 * H + 1] = cmul_tw<INV>(v[Q * R + 2 * H + 1], make_float2(w2.z, w2.w));
             });
         } else if constexpr (L > 1 && TW_LDS) {
             const int k = j & (L - 1);
             constexpr int PO = S::pass_offset(P);
             sfor<R - 1>([&](auto ic) PFB_INLINE {
                 constexpr int i = decltype(ic)::value + 1;
-                v[Q * R + i] = cmul(v[Q * R + i], twp[PO + i * L + k]);
+                v[Q * R + i] = cmul_tw<INV>(v[Q * R + i], twp[PO + i * L + k]);
             });
         } else if constexpr (L > 1) {
             const int k = j & (L - 1);
@@ -318,23 +334,27 @@ __device__ __forceinline__ void fft_pass_compute(int lane, float2 *lds, const fl
                 constexpr int H = decltype(hh)::value;
                 const float4 w2 = wp[H];
                 if constexpr (H > 0)
-                    v[Q * R + 2 * H] = cmul(v[Q * R + 2 * H], make_float2(w2.x, w2.y));
-                v[Q * R + 2 * H + 1] = cmul(v[Q * R + 2 * H + 1], make_float2(w2.z, w2.w));
+                    v[Q * R + 2 * H] = cmul_tw<INV>(v[Q * R + 2 * H], make_float2(w2.x, w2.y));
+                v[Q * R + 2 * H + 1] = cmul_tw<INV>(v[Q * R + 2 * H + 1], make_float2(w2.z, w2.w));
             });
         }
-        Dft<R>::run(&v[Q * R]);
+        Dft<R, INV>::run(&v[Q * R]);
     });
 
     // scatter
     if constexpr (P == S::NPASS - 1) {
         sfor<NB>([&](auto q) PFB_INLINE {
             const int j = lane + G * decltype(q)::value;
-            sfor<R>([&](auto i) PFB_INLINE {
-                float2 t = v[decltype(q)::value * R + decltype(i)::value];
-                if constexpr (INV)
-                    t = conj2(t);
-                dst(j + decltype(i)::value * CR, t);
-            });
+            if constexpr (std::is_same_v<std::decay_t<Dst>, LdsRowDst>) {
+                const int pj = S::pad(j);
+                sfor<R>([&](auto i) PFB_INLINE {
+                    dst.row[S::template pad_at<CR>(j, pj, decltype(i)::value)] = v[decltype(q)::value * R + decltype(i)::value];
+                });
+            } else {
+                sfor<R>([&](auto i) PFB_INLINE {
+                    dst(j + decltype(i)::value * CR, v[decltype(q)::value * R + decltype(i)::value]);
+                });
+            }
         });
     } else {
         sfor<NB>([&](auto q) PFB_INLINE {
@@ -364,8 +384,9 @@ __device__ __forceinline__ void fft_pass(int lane, float2 *lds, const float2 *tw
 
 // The passes of one transform whose first-pass inputs are already in v (see
 // fft_gather_first); `dst(idx, v)` receives output element idx from the last
-// pass. When SRC_IN_LDS the inputs were read from this group's own LDS row,
-// so a multi-wave group synchronises before overwriting it.
+// pass (an LdsRowDst: stored at row[pad(idx)]). When SRC_IN_LDS the inputs
+// were read from this group's own LDS row, so a multi-wave group
+// synchronises before overwriting it.
 //
 // TW_LDS: `tw` points to an LDS copy of the table laid out [pass][i][k]
 // (stage_twiddles_lds), so that the lanes of a butterfly column read
@@ -452,7 +473,7 @@ __device__ __forceinline__ void fft_run(int lane, float2 *lds, const float2 *__r
                                         Dst &&dst)
 {
     float2 v[FftShape<LOG2C, G>::E];
-    fft_gather_first<LOG2C, G, INV>(lane, src, v);
+    fft_gather_first<LOG2C, G>(lane, src, v);
     fft_passes<LOG2C, G, INV, SRC_IN_LDS, TW_LDS>(lane, lds, tw, v, dst);
 }
 

@@ -181,7 +181,7 @@ __global__ __launch_bounds__((1 << LOG2C) / CPT) void fused_fwd_pipe_kernel(Fuse
         asm volatile("" : "+v"(ln));
         const float2 *twp = fft_twiddle_base<true>(tws);
         float2 v[E];
-        fft_gather_first_lds<LOG2C, G, false>(ln, row, v);
+        fft_gather_first_lds<LOG2C, G>(ln, row, v);
         sfor<NPASS>([&](auto pp) PFB_INLINE {
             constexpr int P = decltype(pp)::value;
             if constexpr (P > 0)
