@@ -38,10 +38,15 @@
 
 namespace pfb {
 
-constexpr int BT_THREADS = 512;          // threads per persistent workgroup
+// Two persistent workgroups of four waves share a CU (registers allow two
+// waves per SIMD, LDS two 8192-point rows), so one can run its FIR while the
+// other transforms; a single eight-wave workgroup per CU alternated the two
+// phases (64-beam table 13.5 -> 13.1 ms, same bits). Four waves are also the
+// fewest that hold an 8192-point transform.
+constexpr int BT_THREADS = 256;          // threads per persistent workgroup
 constexpr int BT_WAVES = BT_THREADS / 64;
 constexpr int BT_TASK_ROWS = 32;         // filtered spectra per FIR wave task
-constexpr int BT_LDS = 17408;            // float2: the largest transform round
+constexpr int BT_LDS = 8704;             // float2: the largest transform round (one 8192-point row)
 constexpr int BT_MAX_TAPS = PFB_MAX_TAPS_WINDOW;
 
 struct BeamInfo {
@@ -222,7 +227,7 @@ __device__ __forceinline__ int batched_dispatch_c(const BatchedArgs &a, float2 *
     }
 }
 
-__global__ __launch_bounds__(BT_THREADS, 1) void batched_kernel(BatchedArgs a)
+__global__ __launch_bounds__(BT_THREADS, 2) void batched_kernel(BatchedArgs a)
 {
     __shared__ float2 lds[BT_LDS];
     __shared__ int s_tile;
