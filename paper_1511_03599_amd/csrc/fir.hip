@@ -56,31 +56,74 @@ __global__ __launch_bounds__(256) void gh_partial_kernel(GhArgs a)
     float2 w[TP];
     float2 pf[D];
     float2 pg[D];
-    sfor<TP - 1>([&](auto j) { w[j] = ldx(s_begin + j); });
-    sfor<D>([&](auto k) {
-        if (k < nout) {
-            pf[k] = ldx(s_begin + TP - 1 + k);
-            pg[k] = ldg(s_begin + k);
-        }
-    });
-    for (int base = 0; base < nout; base += U) {
-        sfor<U>([&](auto jjc) {
-            constexpr int jj = decltype(jjc)::value;
-            const int o = base + jj;
-            if (o < nout) {
-                w[(jj + TP - 1) % TP] = pf[jj % D];
-                const float2 g = pg[jj % D];
-                if (o + D < nout) {
-                    pf[jj % D] = ldx(s_begin + o + D + TP - 1);
-                    pg[jj % D] = ldg(s_begin + o + D);
-                }
-                sfor<TP>([&](auto jc) {
-                    constexpr int j = decltype(jc)::value;
-                    const float2 xv = w[(jj + j) % TP];
-                    acc[j] = __builtin_fmaf(g.x, xv.x, __builtin_fmaf(g.y, xv.y, acc[j]));
+    auto fma_row = [&](auto jjc, float2 g) PFB_INLINE {
+        constexpr int jj = decltype(jjc)::value;
+        sfor<TP>([&](auto jc) PFB_INLINE {
+            constexpr int j = decltype(jc)::value;
+            const float2 xv = w[(jj + j) % TP];
+            acc[j] = __builtin_fmaf(g.x, xv.x, __builtin_fmaf(g.y, xv.y, acc[j]));
+        });
+    };
+    // A whole tile inside the stream (every lane's channel, every x row it
+    // reads and a whole number of U-row blocks): every load is issued
+    // unconditionally, so the compiler waits for exactly the row a step
+    // uses. With the tested loads of the general loop below it waited for
+    // every load in flight at each row (4096 channels: 648 us, about one
+    // memory latency per row). Up to 16 taps: the longer windows would
+    // spill with both forms in one kernel.
+    const bool clean = TP <= 16 && (cch + 1) * 64 <= a.C && nout == a.SB && nout % U == 0 &&
+                       s_begin + nout + TP - 2 < in_rows;
+    if (clean) {
+        if constexpr (TP <= 16) {
+            sfor<TP - 1>([&](auto j) PFB_INLINE { w[j] = xb[(s_begin + j) * a.C]; });
+            sfor<D>([&](auto k) PFB_INLINE {
+                pf[k] = xb[(s_begin + TP - 1 + k) * a.C];
+                pg[k] = gb[(s_begin + k) * a.C];
+            });
+            // FULL blocks prefetch D rows ahead for every row (the next block
+            // exists and D <= U); the LAST block only where that stays inside
+            auto block = [&](int base, auto lastc) PFB_INLINE {
+                constexpr bool LASTB = decltype(lastc)::value;
+                sfor<U>([&](auto jjc) PFB_INLINE {
+                    constexpr int jj = decltype(jjc)::value;
+                    const int64_t o = base + jj;
+                    w[(jj + TP - 1) % TP] = pf[jj % D];
+                    const float2 g = pg[jj % D];
+                    if constexpr (!LASTB || jj + D < U) {
+                        pf[jj % D] = xb[(s_begin + o + D + TP - 1) * a.C];
+                        pg[jj % D] = gb[(s_begin + o + D) * a.C];
+                    }
+                    fma_row(jjc, g);
                 });
+            };
+            int base = 0;
+            for (; base + U < nout; base += U)
+                block(base, std::false_type{});
+            block(base, std::true_type{});
+        }
+    } else {
+        sfor<TP - 1>([&](auto j) { w[j] = ldx(s_begin + j); });
+        sfor<D>([&](auto k) {
+            if (k < nout) {
+                pf[k] = ldx(s_begin + TP - 1 + k);
+                pg[k] = ldg(s_begin + k);
             }
         });
+        for (int base = 0; base < nout; base += U) {
+            sfor<U>([&](auto jjc) {
+                constexpr int jj = decltype(jjc)::value;
+                const int o = base + jj;
+                if (o < nout) {
+                    w[(jj + TP - 1) % TP] = pf[jj % D];
+                    const float2 g = pg[jj % D];
+                    if (o + D < nout) {
+                        pf[jj % D] = ldx(s_begin + o + D + TP - 1);
+                        pg[jj % D] = ldg(s_begin + o + D);
+                    }
+                    fma_row(jjc, g);
+                }
+            });
+        }
     }
     if (active) {
         float *pb = a.part + ((int64_t)b * a.n_tiles + tile) * (int64_t)a.T * a.C + c;
