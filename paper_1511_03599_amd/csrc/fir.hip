@@ -19,6 +19,8 @@
 // Rows outside [0, in_rows) read as zero. The same kernel computes the
 // adjoint in the samples (REV: taps reversed, shift = off + T - 1), which is
 // the "full" correlation of the filtered-spectra gradient with the taps.
+#include <algorithm>
+
 #include "fir_launch.h"
 
 namespace pfb {
@@ -26,18 +28,25 @@ namespace pfb {
 // Tap gradient, first stage: per tile of filtered spectra and per channel,
 //   part[tile][t][c] = sum_{s in tile} Re(conj(gy[s][c]) x[s+t][c])
 // with the x window of the lane's channel kept in registers (TP rows).
-template <int TP, int D>
+// FORM: GH_BOTH decides per tile between the branch-free form (a tile
+// wholly inside the stream) and the tested one; GH_CLEAN and GH_TESTED
+// compile one form only, for launches over tiles the host has already
+// split (longer windows, where both forms in one kernel would spill).
+enum { GH_BOTH = 0, GH_CLEAN = 1, GH_TESTED = 2 };
+
+template <int TP, int D, int FORM>
 __global__ __launch_bounds__(256) void gh_partial_kernel(GhArgs a)
 {
     constexpr int U = TP > D ? TP : D;
+    const int run = a.ntiles_run > 0 ? a.ntiles_run : a.n_tiles;
     const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave_id();
-    const int64_t total = (int64_t)a.B * a.n_tiles * a.n_cchunks;
+    const int64_t total = (int64_t)a.B * run * a.n_cchunks;
     if (gw >= total)
         return;
     const int cch = (int)(gw % a.n_cchunks);
     const int64_t rest = gw / a.n_cchunks;
-    const int tile = (int)(rest % a.n_tiles);
-    const int b = (int)(rest / a.n_tiles);
+    const int tile = a.tile0 + (int)(rest % run);
+    const int b = (int)(rest / run);
     const int c = cch * 64 + lane_id();
     const bool active = c < a.C;
     const int64_t s_begin = (int64_t)tile * a.SB;
@@ -69,12 +78,11 @@ __global__ __launch_bounds__(256) void gh_partial_kernel(GhArgs a)
     // unconditionally, so the compiler waits for exactly the row a step
     // uses. With the tested loads of the general loop below it waited for
     // every load in flight at each row (4096 channels: 648 us, about one
-    // memory latency per row). Up to 16 taps: the longer windows would
-    // spill with both forms in one kernel.
-    const bool clean = TP <= 16 && (cch + 1) * 64 <= a.C && nout == a.SB && nout % U == 0 &&
-                       s_begin + nout + TP - 2 < in_rows;
+    // memory latency per row).
+    const bool clean = FORM == GH_CLEAN || (FORM == GH_BOTH && (cch + 1) * 64 <= a.C && nout == a.SB &&
+                                            nout % U == 0 && s_begin + nout + TP - 2 < in_rows);
     if (clean) {
-        if constexpr (TP <= 16) {
+        if constexpr (FORM != GH_TESTED) {
             sfor<TP - 1>([&](auto j) PFB_INLINE { w[j] = xb[(s_begin + j) * a.C]; });
             sfor<D>([&](auto k) PFB_INLINE {
                 pf[k] = xb[(s_begin + TP - 1 + k) * a.C];
@@ -101,7 +109,7 @@ __global__ __launch_bounds__(256) void gh_partial_kernel(GhArgs a)
                 block(base, std::false_type{});
             block(base, std::true_type{});
         }
-    } else {
+    } else if constexpr (FORM != GH_CLEAN) {
         sfor<TP - 1>([&](auto j) { w[j] = ldx(s_begin + j); });
         sfor<D>([&](auto k) {
             if (k < nout) {
@@ -193,15 +201,50 @@ hipError_t launch_fir(const FirArgs &a, int dtype, int tp, int cpt, bool rev, hi
     }
 }
 
-template <int TP> static hipError_t launch_gh_t(const GhArgs &a, hipStream_t st)
+template <int TP, int FORM> static hipError_t launch_gh_run(const GhArgs &a, hipStream_t st)
 {
     constexpr int D = fir_prefetch(TP);
-    const int64_t total = (int64_t)a.B * a.n_tiles * a.n_cchunks;
+    const int run = a.ntiles_run > 0 ? a.ntiles_run : a.n_tiles;
+    const int64_t total = (int64_t)a.B * run * a.n_cchunks;
     const int64_t blocks = (total + 3) / 4;
     if (blocks <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL((gh_partial_kernel<TP, D>), dim3((unsigned)blocks), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((gh_partial_kernel<TP, D, FORM>), dim3((unsigned)blocks), dim3(256), 0, st, a);
     return hipGetLastError();
+}
+
+template <int TP> static hipError_t launch_gh_t(const GhArgs &a, hipStream_t st)
+{
+    if constexpr (TP <= 16) {
+        return launch_gh_run<TP, GH_BOTH>(a, st);
+    } else if constexpr (TP > 32) {
+        return launch_gh_run<TP, GH_TESTED>(a, st); // the branch-free form would halve occupancy
+    } else {
+        // Tiles wholly inside the stream come first: tile t is one iff its
+        // S_B rows are filtered spectra and the x rows it reads, up to
+        // (t+1) S_B + TP - 2, exist (S + T - 1 raw spectra). They take the
+        // branch-free kernel when every channel chunk is whole and a tile is
+        // a whole number of U-row blocks; the rest take the tested one.
+        constexpr int D = fir_prefetch(TP);
+        constexpr int U = TP > D ? TP : D;
+        int64_t n_clean = 0;
+        if (a.C % 64 == 0 && a.SB % U == 0 && a.S + a.T - TP >= 0)
+            n_clean = std::min<int64_t>(a.n_tiles, (a.S + a.T - TP) / a.SB);
+        hipError_t e = hipSuccess;
+        if (n_clean > 0) {
+            GhArgs c = a;
+            c.tile0 = 0;
+            c.ntiles_run = (int)n_clean;
+            e = launch_gh_run<TP, GH_CLEAN>(c, st);
+        }
+        if (e == hipSuccess && n_clean < a.n_tiles) {
+            GhArgs g = a;
+            g.tile0 = (int)n_clean;
+            g.ntiles_run = a.n_tiles - (int)n_clean;
+            e = launch_gh_run<TP, GH_TESTED>(g, st);
+        }
+        return e;
+    }
 }
 
 hipError_t launch_gh(const GhArgs &a, int tp, float *gh, hipStream_t st)

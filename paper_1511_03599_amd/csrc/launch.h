@@ -32,6 +32,8 @@ struct GhArgs {
     int C, T, B;
     int SB, n_tiles, n_cchunks;
     int64_t S;
+    int tile0 = 0;       // first tile of this launch
+    int ntiles_run = 0;  // tiles of this launch (0: all n_tiles)
 };
 
 // Batched C-point transforms of `nrows` rows. Row r lives at

@@ -1,7 +1,9 @@
 """GPU parity of the large transforms over many rows: the split-path filter
 bank forward and adjoint at 2048 to 8192 channels, with enough spectra that
 each persistent transform workgroup (4096 and 8192 channels) takes several
-rows, and the sub-band layout at 4096 channels over many sub-band spectra.
+rows, the split adjoint at 20 and 32 taps over enough spectra that its
+tap-gradient tiles run both the branch-free and the tested kernel, and the
+sub-band layout at 4096 channels over many sub-band spectra.
 Rows are sampled where a workgroup's row sequence starts and steps
 (multiples of 512, 1024 and 2048 and their neighbours), at both ends of the
 streams and at seeded positions, and compared with the oracle (Algorithm 1
@@ -53,7 +55,7 @@ def test_many_row_split_forward(dev, C, T, S, B):
             assert rel_l2(Yh[b, j].astype(np.complex128), want) <= SPEC_TOL, (b, s)
 
 
-@pytest.mark.parametrize("C,T,S", [(4096, 16, 2093), (8192, 4, 1100)])
+@pytest.mark.parametrize("C,T,S", [(4096, 16, 2093), (8192, 4, 1100), (1024, 32, 1100), (1024, 20, 1100)])
 def test_many_row_split_adjoint(dev, C, T, S):
     import torch
     from paper_1511_03599_amd import pfb
