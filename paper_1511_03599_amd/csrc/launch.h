@@ -100,7 +100,7 @@ constexpr int GF_MAX_PASS = 16;
 struct GfftSched {
     int C;
     int npass;
-    int group;           // lanes per row: 64 or 256
+    int group;           // lanes per row: 64, 256 or 512
     int rows_per_block;
     int radix[GF_MAX_PASS];
 };
