@@ -13,10 +13,12 @@
 // m < C, computed in FP64 on the host: W_{RL}^{ik} = table[i k C/(RL)].
 //
 // A group of G lanes owns one row: G = 64 (one wave, several rows per block,
-// no block barriers) for C <= 2048, G = 256 (one row per block) up to 4096,
-// G = 512 above: the two LDS buffers of a larger row leave room for one
-// block per CU, which then holds eight waves instead of four (6144 channels,
-// T=16, 2^27 samples: 1.65 -> 1.36 ms; 7168 channels 1.58 -> 1.32 ms).
+// no block barriers) up to C = 1024, G = 256 (one row per block) up to 4096,
+// G = 512 above. The two LDS buffers of a row limit how many rows a CU
+// holds, so the larger rows take more lanes to keep enough waves in flight
+// (T=16, 2^27 samples: 1536 channels 1.32 -> 1.03 ms with 256 lanes instead
+// of 64; 6144 channels 1.65 -> 1.36 ms and 7168 1.58 -> 1.32 ms with 512
+// instead of 256; 768 channels stay faster with 64).
 #include <algorithm>
 
 #include "fft_device.h"
@@ -194,7 +196,7 @@ bool gfft_schedule(int C, GfftSched *s)
     if (rem != 1 || np < 2) // the kernel's first and last passes are distinct
         return false;
     t.npass = np;
-    t.group = C <= 2048 ? 64 : C <= 4096 ? 256 : 512;
+    t.group = C <= 1024 ? 64 : C <= 4096 ? 256 : 512;
     const int64_t row_lds = (int64_t)2 * C * 8;
     int f = 1;
     if (t.group == 64)

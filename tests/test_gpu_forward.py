@@ -249,7 +249,8 @@ def test_chunked_split_equals_whole_split(dev, C, T, S, B, mib, tmp_path, monkey
     assert np.array_equal(a, b)
 
 
-MIXED = [(96, 8), (105, 4), (384, 16), (1000, 5), (3072, 16), (2401, 3), (6144, 8), (3125, 2), (448, 32)]
+MIXED = [(96, 8), (105, 4), (384, 16), (1000, 5), (3072, 16), (2401, 3), (6144, 8), (3125, 2), (448, 32),
+         (1536, 12), (1344, 6), (7168, 4)]
 
 
 @pytest.mark.parametrize("C,T", MIXED)
