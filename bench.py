@@ -13,7 +13,8 @@ plain comparator (unfused FIR launch then FFT launch, split adjoint) is timed
 beside it, and the oracle is timed on bounded samples on the host cores.
 Unless --quick is given, `extras` adds the other workloads: the forward pass
 over T in {4..64} at C=1024 (one stream of 65536 spectra, also timed fwd+bwd),
-the low-precision inputs at C=4096 with their errors against FP64, the
+the split adjoint where no fused kernel applies (C=4096 at T=16, C=1024 at
+T=32), the low-precision inputs at C=4096 with their errors against FP64, the
 64-beam batched launch against 64 separate plain launches, and the layouts
 of the later rows (streaming, non-power-of-two channel counts, sub-bands).
 
@@ -445,6 +446,32 @@ def extras_subbands(dev, stream):
     return out
 
 
+def extras_split_adjoint(dev, stream):
+    """The adjoint where no fused kernel applies (split path: inverse
+    transform, reversed-tap FIR, tap-gradient partials and reduction), one
+    complex64 stream of 2^27 samples: C=4096 at T=16 and C=1024 at T=32.
+    GB/s counts the adjoint's minimum bytes (read gY and x, write gx)."""
+    import torch
+    from paper_1511_03599_amd import metrics, pfb, synth
+    out = {}
+    for C, T in ((4096, 16), (1024, 32)):
+        S = (1 << 27) // C
+        x = synth.device_noise((1, S + T - 1, C), 1511700 + C, dev)
+        h = torch.from_numpy(synth.windowed_sinc_taps(C, T)).to(dev)
+        gY = synth.device_noise((1, S, C), 1511800 + C, dev)
+        gx = torch.empty_like(x)
+        gh = torch.empty((T, C), dtype=torch.float32, device=dev)
+        p = pfb.Plan(C, T, S, 1, "c64")
+        for _ in range(2):
+            p.backward(x, h, gY, gx=gx, gh=gh)
+        t = time_calls(lambda: p.backward(x, h, gY, gx=gx, gh=gh), 10, stream)
+        bb = metrics.backward_fused_bytes(1, S, C, T)
+        out[f"c{C}_t{T}"] = {"bwd_ms": round(t, 4), "backward_kind": p.info()["backward_kind"],
+                             "min_bytes_gbs": round(bb / t / 1e6, 1)}
+        del p, x, gY, gx
+    return out
+
+
 def extras_single_stream(dev, stream):
     """One stream of 65536 spectra, C=1024, T=16 (the tap-sweep workload at
     16 taps): forward, adjoint and the fwd+bwd step, complex64 noise."""
@@ -618,6 +645,9 @@ def main():
         extras = {"tap_sweep_c1024_s65536": extras_sweep(dev, stream, 1024, 65536)}
         log("bench: single stream fwd+bwd")
         extras["single_stream_b1_s65536_c1024_t16"] = extras_single_stream(dev, stream)
+        torch.cuda.empty_cache()
+        log("bench: split adjoint")
+        extras["split_adjoint_2p27"] = extras_split_adjoint(dev, stream)
         torch.cuda.empty_cache()
         log("bench: low-precision inputs")
         extras["precision_c4096_t16_s32768"] = extras_precision(dev, stream)
