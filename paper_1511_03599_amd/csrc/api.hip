@@ -429,7 +429,9 @@ static pfb_status plan_single(const pfb_desc *d, pfb_plan *p)
                 st = dev_alloc(reinterpret_cast<void **>(&p->ws_gy), p->ws_gy_bytes, "backward workspace");
                 if (st != PFB_OK)
                     return st;
-                parts = (int64_t)d->batch * ceil_div(d->spectra, p->gh_sb);
+                // tiles of gh_sb filtered spectra (gh_partial_kernel) or of
+                // gh_sb raw spectra (gxgh_kernel), whichever is more
+                parts = (int64_t)d->batch * ceil_div(d->spectra + d->taps - 1, p->gh_sb);
             }
             p->ws_gh_bytes = parts * d->taps * d->channels * 4;
             st = dev_alloc(reinterpret_cast<void **>(&p->ws_gh), p->ws_gh_bytes, "tap-gradient partials");
@@ -789,6 +791,25 @@ extern "C" pfb_status pfb_backward(pfb_plan *p, const void *x, const float *taps
     e = run_fft(p, reinterpret_cast<const float2 *>(gY), p->ws_gy, (int64_t)d.batch * S, S, S * C, S * C, true, st);
     if (e != hipSuccess)
         return hip_fail(e, "inverse FFT launch");
+    // 2 and 3 in one pass when both are wanted (up to 16 taps): gy and x are
+    // read once for the sample gradient and the tap-gradient partials
+    if (gx && gh && p->tp <= 16) {
+        GxGhArgs a{};
+        a.x = reinterpret_cast<const float2 *>(x);
+        a.gy = p->ws_gy;
+        a.h = taps;
+        a.gx = reinterpret_cast<float2 *>(gx);
+        a.part = p->ws_gh;
+        a.C = d.channels;
+        a.T = d.taps;
+        a.B = d.batch;
+        a.SB = p->gh_sb;
+        a.n_tiles = (int)ceil_div(S + T - 1, a.SB);
+        a.n_cchunks = (int)ceil_div(C, 64);
+        a.S = S;
+        e = launch_gxgh(a, p->tp, gh, st);
+        return e == hipSuccess ? PFB_OK : hip_fail(e, "adjoint launch");
+    }
     // 2. gx = adjoint FIR: reversed taps over gy, zero outside [0, S)
     if (gx) {
         FirArgs a{};

@@ -142,6 +142,135 @@ __global__ __launch_bounds__(256) void gh_partial_kernel(GhArgs a)
     }
 }
 
+// Sample gradient and tap-gradient partials in one pass (the split adjoint
+// when both are wanted, up to 16 taps): per tile of raw spectra p and per
+// channel, with the window of the last TP rows of gy in registers,
+//   gx[p][c] = sum_{t < T} h[t][c] gy[p - t][c]           (gy = 0 outside [0, S))
+//   part[tile][t][c] = sum_{p in tile} Re(conj(gy[p - t][c]) x[p][c])
+// so gy is read once for both, and x once: 24 bytes per sample instead of
+// the 32 of the reversed-tap FIR and gh_partial_kernel run one after the
+// other. Window slot j of output p holds gy[p - (TP-1) + j], which carries
+// tap t = TP-1-j. Tiles wholly inside the stream run with unconditional
+// loads and stores, the others with tested ones.
+template <int TP, int D>
+__global__ __launch_bounds__(256) void gxgh_kernel(GxGhArgs a)
+{
+    constexpr int U = TP > D ? TP : D;
+    static_assert(U % TP == 0 && U % D == 0, "static window and prefetch slots");
+    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave_id();
+    const int64_t total = (int64_t)a.B * a.n_tiles * a.n_cchunks;
+    if (gw >= total)
+        return;
+    const int cch = (int)(gw % a.n_cchunks);
+    const int64_t rest = gw / a.n_cchunks;
+    const int tile = (int)(rest % a.n_tiles);
+    const int b = (int)(rest / a.n_tiles);
+    const int c = cch * 64 + lane_id();
+    const bool active = c < a.C;
+    const int64_t rows = a.S + a.T - 1;
+    const int64_t p0 = (int64_t)tile * a.SB;
+    const int np = (int)((rows - p0) < a.SB ? (rows - p0) : a.SB);
+    const float2 *xb = a.x + (int64_t)b * rows * a.C + c;
+    const float2 *gb = a.gy + (int64_t)b * a.S * a.C + c;
+    float2 *gxb = a.gx + (int64_t)b * rows * a.C + c;
+    const int off = TP - a.T;
+
+    float hp[TP];
+    sfor<TP>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        hp[j] = (active && j >= off) ? a.h[(int64_t)(TP - 1 - j) * a.C + c] : 0.0f;
+    });
+    float acc[TP];
+    sfor<TP>([&](auto j) { acc[j] = 0.0f; });
+    float2 w[TP];
+    float2 pg[D], px[D];
+
+    // output row o = base + jj of the tile: gy row p0 + o enters the window,
+    // x row p0 + o is consumed, gx row p0 + o is computed
+    auto step = [&](auto jjc, float2 g_new, float2 xv, float2 &g_out) PFB_INLINE {
+        constexpr int jj = decltype(jjc)::value;
+        w[(jj + TP - 1) % TP] = g_new;
+        float gr = 0.0f, gi = 0.0f;
+        sfor<TP>([&](auto jc) PFB_INLINE {
+            constexpr int j = decltype(jc)::value;
+            const float2 v = w[(jj + j) % TP];
+            gr = __builtin_fmaf(hp[j], v.x, gr);
+            gi = __builtin_fmaf(hp[j], v.y, gi);
+            acc[j] = __builtin_fmaf(v.x, xv.x, __builtin_fmaf(v.y, xv.y, acc[j]));
+        });
+        g_out = make_float2(gr, gi);
+    };
+
+    const bool clean = (cch + 1) * 64 <= a.C && np == a.SB && np % U == 0 && p0 - (TP - 1) >= 0 &&
+                       p0 + np <= a.S;
+    if (clean) {
+        sfor<TP - 1>([&](auto k) PFB_INLINE { w[k] = gb[(p0 - (TP - 1) + k) * a.C]; });
+        sfor<D>([&](auto k) PFB_INLINE {
+            pg[k] = gb[(p0 + k) * a.C];
+            px[k] = xb[(p0 + k) * a.C];
+        });
+        // FULL blocks prefetch D rows ahead for every row (the next block
+        // exists and D <= U); the LAST block only where that stays inside
+        auto block = [&](int base, auto lastc) PFB_INLINE {
+            constexpr bool LASTB = decltype(lastc)::value;
+            sfor<U>([&](auto jjc) PFB_INLINE {
+                constexpr int jj = decltype(jjc)::value;
+                const int64_t p = p0 + base + jj;
+                const float2 g_new = pg[jj % D], xv = px[jj % D];
+                if constexpr (!LASTB || jj + D < U) {
+                    pg[jj % D] = gb[(p + D) * a.C];
+                    px[jj % D] = xb[(p + D) * a.C];
+                }
+                float2 g;
+                step(jjc, g_new, xv, g);
+                store_nt(gxb + p * a.C, g);
+            });
+        };
+        int base = 0;
+        for (; base + U < np; base += U)
+            block(base, std::false_type{});
+        block(base, std::true_type{});
+    } else {
+        auto ldg = [&](int64_t q) -> float2 {
+            return (active && q >= 0 && q < a.S) ? gb[q * a.C] : make_float2(0.0f, 0.0f);
+        };
+        auto ldx = [&](int64_t p) -> float2 { return (active && p < rows) ? xb[p * a.C] : make_float2(0.0f, 0.0f); };
+        sfor<TP - 1>([&](auto k) { w[k] = ldg(p0 - (TP - 1) + k); });
+        sfor<D>([&](auto k) {
+            if (k < np) {
+                pg[k] = ldg(p0 + k);
+                px[k] = ldx(p0 + k);
+            }
+        });
+        for (int base = 0; base < np; base += U) {
+            sfor<U>([&](auto jjc) {
+                constexpr int jj = decltype(jjc)::value;
+                const int o = base + jj;
+                if (o < np) {
+                    const float2 g_new = pg[jj % D], xv = px[jj % D];
+                    if (o + D < np) {
+                        pg[jj % D] = ldg(p0 + o + D);
+                        px[jj % D] = ldx(p0 + o + D);
+                    }
+                    float2 g;
+                    step(jjc, g_new, xv, g);
+                    if (active)
+                        store_nt(gxb + (p0 + o) * a.C, g);
+                }
+            });
+        }
+    }
+    if (active) {
+        float *pb = a.part + ((int64_t)b * a.n_tiles + tile) * (int64_t)a.T * a.C + c;
+        sfor<TP>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            constexpr int t = TP - 1 - j;
+            if (t < a.T)
+                pb[(int64_t)t * a.C] = acc[j];
+        });
+    }
+}
+
 // Tap gradient, second stage: gh[t][c] = sum over all tiles of the partials.
 // Tile p goes to running sum p mod 4 (each sum takes its tiles in ascending
 // order), and the four sums are combined as (s0 + s1) + (s2 + s3): a fixed
@@ -256,6 +385,30 @@ hipError_t launch_gh(const GhArgs &a, int tp, float *gh, hipStream_t st)
     case 16: e = launch_gh_t<16>(a, st); break;
     case 32: e = launch_gh_t<32>(a, st); break;
     case 64: e = launch_gh_t<64>(a, st); break;
+    default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess)
+        return e;
+    return launch_gh_reduce(a.part, gh, (int64_t)a.B * a.n_tiles, (int64_t)a.T * a.C, st);
+}
+
+template <int TP> static hipError_t launch_gxgh_t(const GxGhArgs &a, hipStream_t st)
+{
+    const int64_t total = (int64_t)a.B * a.n_tiles * a.n_cchunks;
+    const int64_t blocks = (total + 3) / 4;
+    if (blocks <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL((gxgh_kernel<TP, 16>), dim3((unsigned)blocks), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_gxgh(const GxGhArgs &a, int tp, float *gh, hipStream_t st)
+{
+    hipError_t e;
+    switch (tp) {
+    case 4: e = launch_gxgh_t<4>(a, st); break;
+    case 8: e = launch_gxgh_t<8>(a, st); break;
+    case 16: e = launch_gxgh_t<16>(a, st); break;
     default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess)

@@ -36,6 +36,19 @@ struct GhArgs {
     int ntiles_run = 0;  // tiles of this launch (0: all n_tiles)
 };
 
+// Sample gradient and tap-gradient partials of the split adjoint in one pass
+// over tiles of S_B raw spectra (rows of gx).
+struct GxGhArgs {
+    const float2 *x;     // [B][S+T-1][C]
+    const float2 *gy;    // [B][S][C]
+    const float *h;      // [T][C]
+    float2 *gx;          // [B][S+T-1][C]
+    float *part;         // [B*n_tiles][T][C]
+    int C, T, B;
+    int SB, n_tiles, n_cchunks;
+    int64_t S;
+};
+
 // Batched C-point transforms of `nrows` rows. Row r lives at
 // in + (r / rows_per_group)*in_gstride + (r % rows_per_group)*C, and likewise
 // for out.
@@ -86,6 +99,8 @@ hipError_t launch_fir_adjoint(const FirArgs &a, int tp, int cpt, hipStream_t st)
 // channel per lane (64 per wave task), no tap padding (shift = 0).
 hipError_t launch_fir_long(const FirArgs &a, int dtype, hipStream_t st);
 hipError_t launch_gh(const GhArgs &a, int tp, float *gh, hipStream_t st);
+// padded taps tp <= 16; also runs the reduction into gh
+hipError_t launch_gxgh(const GxGhArgs &a, int tp, float *gh, hipStream_t st);
 hipError_t launch_fft(const FftArgs &a, int log2c, bool inv, hipStream_t st);
 // Forward transforms of polarisation-interleaved sub-bands: a.nrows =
 // spectra * nsub * 2 rows, row r at a.in + (r/2)*2C + (r%2), element stride 2
