@@ -791,9 +791,9 @@ extern "C" pfb_status pfb_backward(pfb_plan *p, const void *x, const float *taps
     e = run_fft(p, reinterpret_cast<const float2 *>(gY), p->ws_gy, (int64_t)d.batch * S, S, S * C, S * C, true, st);
     if (e != hipSuccess)
         return hip_fail(e, "inverse FFT launch");
-    // 2 and 3 in one pass when both are wanted (up to 16 taps): gy and x are
+    // 2 and 3 in one pass when both are wanted (up to 32 taps): gy and x are
     // read once for the sample gradient and the tap-gradient partials
-    if (gx && gh && p->tp <= 16) {
+    if (gx && gh && p->tp <= 32) {
         GxGhArgs a{};
         a.x = reinterpret_cast<const float2 *>(x);
         a.gy = p->ws_gy;

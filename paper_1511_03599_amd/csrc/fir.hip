@@ -143,7 +143,7 @@ __global__ __launch_bounds__(256) void gh_partial_kernel(GhArgs a)
 }
 
 // Sample gradient and tap-gradient partials in one pass (the split adjoint
-// when both are wanted, up to 16 taps): per tile of raw spectra p and per
+// when both are wanted, up to 32 taps): per tile of raw spectra p and per
 // channel, with the window of the last TP rows of gy in registers,
 //   gx[p][c] = sum_{t < T} h[t][c] gy[p - t][c]           (gy = 0 outside [0, S))
 //   part[tile][t][c] = sum_{p in tile} Re(conj(gy[p - t][c]) x[p][c])
@@ -398,7 +398,7 @@ template <int TP> static hipError_t launch_gxgh_t(const GxGhArgs &a, hipStream_t
     const int64_t blocks = (total + 3) / 4;
     if (blocks <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL((gxgh_kernel<TP, 16>), dim3((unsigned)blocks), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((gxgh_kernel<TP, TP <= 16 ? 16 : 8>), dim3((unsigned)blocks), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
@@ -409,6 +409,7 @@ hipError_t launch_gxgh(const GxGhArgs &a, int tp, float *gh, hipStream_t st)
     case 4: e = launch_gxgh_t<4>(a, st); break;
     case 8: e = launch_gxgh_t<8>(a, st); break;
     case 16: e = launch_gxgh_t<16>(a, st); break;
+    case 32: e = launch_gxgh_t<32>(a, st); break;
     default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess)

@@ -99,7 +99,7 @@ hipError_t launch_fir_adjoint(const FirArgs &a, int tp, int cpt, hipStream_t st)
 // channel per lane (64 per wave task), no tap padding (shift = 0).
 hipError_t launch_fir_long(const FirArgs &a, int dtype, hipStream_t st);
 hipError_t launch_gh(const GhArgs &a, int tp, float *gh, hipStream_t st);
-// padded taps tp <= 16; also runs the reduction into gh
+// padded taps tp <= 32; also runs the reduction into gh
 hipError_t launch_gxgh(const GxGhArgs &a, int tp, float *gh, hipStream_t st);
 hipError_t launch_fft(const FftArgs &a, int log2c, bool inv, hipStream_t st);
 // Forward transforms of polarisation-interleaved sub-bands: a.nrows =
