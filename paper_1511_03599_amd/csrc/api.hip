@@ -334,9 +334,18 @@ static pfb_status plan_single(const pfb_desc *d, pfb_plan *p)
     // Longer windows re-read T-1 halo rows per tile, so their tiles are
     // longer: 128 rows at 32 taps (1024 channels: 0.25 -> 0.22 ms), 64 rows
     // at 64 taps (faster than 32 or 128).
+    // From 2048 channels complex64 input, and from 4096 int8 input, run
+    // faster with one channel per lane and 32-row tiles (twice the waves;
+    // T=16, 2^27 samples: complex64 FIR 0.393 -> 0.381 ms at 2048 channels,
+    // 0.391 -> 0.377 at 4096, 0.398 -> 0.376 at 8192; int8 0.280 -> 0.26 at
+    // 4096, 0.273 -> 0.267 at 8192); int16 and fp16 input do not gain.
     const bool cpt2_ok = p->tp <= 16 && d->channels % 2 == 0;
-    p->fir_cpt = cpt2_ok ? 2 : 1;
-    p->fir_sb = p->tp >= 64 ? 64 : p->tp == 32 ? 128 : (d->dtype == PFB_CI8 && p->tp == 16) ? 64 : 32;
+    const bool wide_one = (d->dtype == PFB_C64 && d->channels >= 2048) || (d->dtype == PFB_CI8 && d->channels >= 4096);
+    p->fir_cpt = cpt2_ok && !wide_one ? 2 : 1;
+    p->fir_sb = p->tp >= 64                                          ? 64
+                : p->tp == 32                                        ? 128
+                : (d->dtype == PFB_CI8 && p->tp == 16 && !wide_one) ? 64
+                                                                     : 32;
     if (tuned) {
         if (te.fir_cpt == 1 || (te.fir_cpt == 2 && cpt2_ok))
             p->fir_cpt = te.fir_cpt;
