@@ -1,5 +1,5 @@
 """GPU parity of the large transforms over many rows: the split-path filter
-bank forward and adjoint at 2048 to 8192 channels, with enough spectra that
+bank forward and adjoint at 1024 to 8192 channels, with enough spectra that
 each persistent transform workgroup (4096 and 8192 channels) takes several
 rows, the split adjoint at 20 and 32 taps over enough spectra that its
 tap-gradient tiles run both the branch-free and the tested kernel, and the
@@ -35,7 +35,7 @@ def sample_rows(n, seed, count):
     return sorted(set(rows) | extra)
 
 
-@pytest.mark.parametrize("C,T,S,B", [(2048, 16, 4133, 1), (4096, 16, 2093, 1), (8192, 8, 1100, 2)])
+@pytest.mark.parametrize("C,T,S,B", [(2048, 16, 4133, 1), (4096, 16, 2093, 1), (8192, 8, 1100, 2), (1024, 32, 8300, 1)])
 def test_many_row_split_forward(dev, C, T, S, B):
     import torch
     from paper_1511_03599_amd import pfb
@@ -55,7 +55,8 @@ def test_many_row_split_forward(dev, C, T, S, B):
             assert rel_l2(Yh[b, j].astype(np.complex128), want) <= SPEC_TOL, (b, s)
 
 
-@pytest.mark.parametrize("C,T,S", [(4096, 16, 2093), (8192, 4, 1100), (1024, 32, 1100), (1024, 20, 1100)])
+@pytest.mark.parametrize("C,T,S", [(4096, 16, 2093), (8192, 4, 1100), (1024, 32, 1100), (1024, 20, 1100),
+                                   (1024, 24, 8300)])
 def test_many_row_split_adjoint(dev, C, T, S):
     import torch
     from paper_1511_03599_amd import pfb
